@@ -1,0 +1,172 @@
+"""Benchmark: lnL + all-branch-gradient evaluations per second on one MI355X.
+
+A step is one full evaluation of the hot path on the 128-taxon GTR workload (100,000
+patterns, 4 gamma categories, FP32, rescaling every 4 levels): transition matrices for
+all 254 branches, post-order partials, root integration, pre-order partials and all 254
+branch gradients, with the inputs resident in HBM.  Each step uses a different set of
+branch lengths (multiplicative N(0, 0.05) perturbations, as an MCMC proposal would).
+
+Prints one JSON line (rank 0, N = 1) with the throughput, the roofline of the dominant
+kernel (the traversal kernel, timed live with HIP events on the library's stream), the
+error against the FP64 oracle, synchronous-call latency percentiles and the oracle timed
+on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "lnL+gradient evals/s vs plain FP32 at stated error; %roofline; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(n_tips: int, n_patterns: int, n_states: int, n_cat: int, elem: int) -> float:
+    """Bytes one full evaluation must move with per-operation accounting: each of the N-2
+    non-root internal nodes' partials is written and read once in the post-order pass and
+    read (pre_n), read (post) and written (pre_c) in the pre-order pass - 5 (N-2) E b - plus
+    the tip states read once in each pass (2 N P bytes).  E = P K S (algorithmic S)."""
+    E = n_patterns * n_cat * n_states
+    return 5.0 * (n_tips - 2) * E * elem + 2.0 * n_tips * n_patterns
+
+
+def cpu_baseline(wl, sample_patterns: int):
+    """The FP64 oracle on the first `sample_patterns` patterns, one thread, scaled to evals/s
+    of the full workload."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    tips = wl.tips[:, :sample_patterns]
+    w = wl.weights[:sample_patterns]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.lnl_and_grad(wl.tree.children, wl.n_tips, wl.t, wl.Q, wl.pi, wl.rates,
+                            wl.cat_weights, tips, w)
+        dt = time.perf_counter() - t0
+    full = dt * wl.n_patterns / sample_patterns
+    return {"value": 1.0 / full, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_patterns} of {wl.n_patterns} patterns of the same workload, "
+                      f"lnL + all {2 * wl.n_tips - 2} gradients, FP64 NumPy/SciPy, 1 thread; "
+                      f"{dt:.1f} s measured, scaled by patterns",
+            "seconds_per_eval": full,
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="nuc128")
+    ap.add_argument("--precision", default="f32")
+    ap.add_argument("--cpu-sample", type=int, default=60000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-samples", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the pattern "
+              "partition across GPUs is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_27607_amd import Instance
+
+    print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
+    wl = synth.config_workload(args.workload)
+    N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
+    nb = 2 * N - 2
+    period = max(1, wl.meta.get("scale_every", 4))
+    inst = Instance(N, P, S, K, precision=args.precision, scaling="every_k", scale_period=period)
+    inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
+              children=wl.tree.children)
+    dev = inst.device
+    rng = np.random.default_rng(1)
+    n_sets = args.steps + args.warmup
+    t_all = wl.t[:nb][None, :] * np.exp(0.05 * rng.standard_normal((n_sets, nb)))
+    t_dev = torch.tensor(t_all, dtype=torch.float64, device=dev)
+    out = torch.empty((n_sets, 1 + nb), dtype=torch.float64, device=dev)
+
+    # accuracy at the workload's own branch lengths
+    lnl, g = inst.evaluate(wl.t)
+    err = {}
+    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+        gg = np.array(gold["grad"])
+        err = {"lnl_rel": abs(lnl - gold["lnl"]) / abs(gold["lnl"]),
+               "lnl_abs": abs(lnl - gold["lnl"]),
+               "grad_maxabs_over_maxabs": float(np.max(np.abs(g - gg)) / np.max(np.abs(gg))),
+               "grad_l2_rel": float(np.linalg.norm(g - gg) / np.linalg.norm(gg)),
+               "reference": "FP64 oracle, full workload"}
+
+    print("[bench] warmup", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    torch.cuda.synchronize()
+    inst.status()
+
+    print("[bench] timed region", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, n_sets):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    inst.status()
+    ms_per_step = 1000.0 * elapsed / args.steps
+
+    # the same steps again with every kernel bracketed by HIP events on the library's stream
+    inst.profile(True)
+    inst.profile_read()
+    for i in range(args.warmup, n_sets):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    prof = inst.profile_read()
+    inst.profile(False)
+    trav_ms = prof["traversal"][0] / max(1, prof["traversal"][1])
+    elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.precision]
+    alg = algorithmic_bytes(N, P, S, K, elem)
+    achieved = alg / (trav_ms * 1e-3) / 1e9
+
+    # synchronous latency: host branch lengths in, lnL + gradients on the host out
+    lat = []
+    for i in range(args.latency_samples):
+        s = time.perf_counter()
+        inst.evaluate(t_all[i % n_sets])
+        lat.append(1000.0 * (time.perf_counter() - s))
+
+    line = {
+        "metric": METRIC, "value": 1000.0 / ms_per_step, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N}-taxon Yule tree, {wl.meta['kind'].upper()}+G{K} "
+                               f"(alpha 0.5), {P} simulated patterns, S={S}, rescaling every "
+                               f"{period} levels, lnL + all {nb} branch gradients per eval",
+                   "taxa": N, "patterns": P, "states": S, "categories": K,
+                   "precision": args.precision, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "walk_small (fused post-order + root + pre-order + gradients)",
+                     "kernel_ms": trav_ms, "algorithmic_bytes": alg},
+        "kernels_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+        "error_vs_oracle": err,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mode": "synchronous hp_evaluate, host in/out"},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, P))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

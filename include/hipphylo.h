@@ -1,0 +1,241 @@
+/*
+ * hipphylo - phylogenetic log-likelihoods and branch-length gradients on AMD Instinct MI355X.
+ *
+ * C ABI of the library.  The calls follow the paper's statement of the problem
+ * (BEAGLE 4.1, Introduction and Key Improvements): a client sets tip states and
+ * pattern weights, sets the eigensystem of the rate matrix, the category rates
+ * and the stationary frequencies, updates the cached transition-probability
+ * matrices P(t) = V exp(diag(lam) r t) V^-1 (Discussion: matrices come from an
+ * eigendecomposition and are cached across patterns), updates post-order
+ * partial likelihoods over an operation list (Felsenstein's pruning, cited in
+ * the Introduction), integrates the root, and runs the pre-order traversal
+ * whose partials give the gradient with respect to every branch length as a
+ * pre . Q . post sandwich in one linear-time pass (Algorithmic advances;
+ * Discussion).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns an int: HP_OK (0) or a negative HP_ERR_* code.  No C++
+ *    exception crosses this boundary.  hp_last_error() returns the message of
+ *    the most recent failure on an instance.
+ *  - Node/buffer numbering: tips are 0..n_tips-1.  Post-order partial buffers
+ *    are addressed as n_tips..n_tips+n_partials-1 (so a tree's internal node v
+ *    can use post buffer v); pre-order partial buffers are 0..n_partials-1.
+ *  - Partials are stored on the device as [category][pattern][state] with the
+ *    pattern count padded to a multiple of 64 and the state count padded
+ *    (hp_query HP_Q_STATE_PAD, HP_Q_PATTERN_PAD); padding patterns carry weight
+ *    0 and an unknown state at every tip, so they contribute exactly nothing.
+ *  - Device memory: the library never allocates device memory.  The caller
+ *    sizes a workspace with hp_workspace_bytes, allocates it (any allocator) and
+ *    passes it to hp_create; it must outlive the instance.  Host arrays passed to
+ *    any call are borrowed for the duration of the call only.
+ *  - Streams: all device work is ordered on the instance's HIP stream
+ *    (hp_set_stream).  Calls that return results in host memory synchronise that
+ *    stream; the *_device variants only enqueue.
+ *  - An instance is not thread-safe.  Distinct instances on distinct streams do
+ *    not affect each other, and results are bitwise reproducible (all pattern
+ *    sums are fixed-order two-stage FP64 reductions, no floating-point atomics).
+ */
+#ifndef HIPPHYLO_H
+#define HIPPHYLO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+#define HP_OK               0
+#define HP_ERR_ARG         -1  /* NULL pointer, bad count or malformed descriptor            */
+#define HP_ERR_INDEX       -2  /* buffer, matrix, eigen, tip or gradient index out of range    */
+#define HP_ERR_VALUE       -3  /* NaN/Inf/negative branch length or weight, state > S,
+                                  frequencies not summing to 1 within 1e-9                    */
+#define HP_ERR_UNSUPPORTED -4  /* state-count / precision / category-count combination        */
+#define HP_ERR_WORKSPACE   -5  /* workspace missing, misaligned or smaller than required       */
+#define HP_ERR_STATE       -6  /* a required input (eigensystem, tree, ...) was never set      */
+#define HP_ERR_DEVICE      -7  /* a HIP runtime error; hp_last_error() carries its string      */
+#define HP_ERR_NUMERIC     -8  /* a site likelihood was 0 or not finite (lnL written as -inf) */
+
+/* ---------------------------------------------------------------- precisions */
+#define HP_PREC_F64   0  /* partials and arithmetic in FP64                                    */
+#define HP_PREC_F32   1  /* partials and arithmetic in FP32 (the plain single-precision form)  */
+#define HP_PREC_BF16  2  /* partials stored in BF16, partials x P(t) on MFMA, FP32 accumulation */
+#define HP_PREC_F16   3  /* partials stored in FP16, partials x P(t) on MFMA, FP32 accumulation */
+
+/* ---------------------------------------------------------------- rescaling policies
+ * Rescaling multiplies a node's partials for one pattern by 2^-e, e being the
+ * binary exponent of their maximum over categories and states, so the maximum
+ * lands in [0.5, 1).  This is exact in binary floating point; the exponents of
+ * post-order partials are accumulated per pattern in int32 and added back as
+ * e * ln 2 at the root, those of pre-order partials cancel in the gradient. */
+#define HP_SCALE_NONE          0  /* never rescale (FP64 on small trees)                     */
+#define HP_SCALE_EVERY_NODE    1  /* rescale every post- and pre-order partial                */
+#define HP_SCALE_EVERY_K_LEVELS 2 /* post: rescale a node once k internal nodes have been
+                                     combined without rescaling along some path below it
+                                     (every root-to-tip path is rescaled at least every k
+                                     levels); pre: every node                               */
+
+typedef struct hp_desc {
+    int32_t n_tips;        /* N >= 2                                                    */
+    int32_t n_patterns;    /* P >= 1                                                    */
+    int32_t n_states;      /* S in [2, 64]                                              */
+    int32_t n_categories;  /* K in [1, 8]                                               */
+    int32_t n_partials;    /* internal partial buffers (>= N-1 for hp_set_tree)         */
+    int32_t n_matrices;    /* transition-matrix slots (>= 2N-2 for hp_set_tree)         */
+    int32_t n_eigen;       /* eigensystem / frequency slots, >= 1                       */
+    int32_t precision;     /* HP_PREC_*                                                 */
+    int32_t scaling;       /* HP_SCALE_*                                                */
+    int32_t scale_period;  /* k for HP_SCALE_EVERY_K_LEVELS (>= 1), ignored otherwise    */
+    int32_t device;        /* HIP device ordinal the workspace lives on                 */
+} hp_desc;
+
+typedef struct hp_instance hp_instance;
+
+/* Post-order operation: dest = (P[mat1] child1) * (P[mat2] child2) per category and pattern.
+ * child < n_tips reads that tip's states; otherwise it names a post buffer.  dest is a
+ * post buffer index (>= n_tips).  rescale: 1 to rescale dest (its exponent joins the
+ * cumulative exponent that every post buffer carries for its subtree), 0 not to. */
+typedef struct hp_post_op {
+    int32_t dest, child1, mat1, child2, mat2, rescale;
+} hp_post_op;
+
+/* Pre-order operation for one parent with two children.  parent_pre < 0 means the parent
+ * is the root (its pre-order partial is the frequency vector); otherwise it names a pre
+ * buffer.  childX_post names the child's post buffer or tip; matX the matrix of the edge
+ * above the child; childX_pre the pre buffer that receives the child's pre-order partial
+ * (< 0: not stored, e.g. for tips); gradX the slot of out_grad receiving the derivative of
+ * lnL with respect to that edge's length (< 0: not computed).  Gradient slots must be
+ * distinct within one list. */
+typedef struct hp_pre_op {
+    int32_t parent_pre;
+    int32_t child1_post, mat1, child1_pre, grad1;
+    int32_t child2_post, mat2, child2_pre, grad2;
+} hp_pre_op;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+/* Bytes of device workspace an instance with this descriptor needs (256-byte aligned). */
+int hp_workspace_bytes(const hp_desc* desc, size_t* out_bytes);
+
+/* Create an instance on desc->device using the caller's workspace (device pointer,
+ * 256-byte aligned, at least hp_workspace_bytes).  hip_stream may be NULL (the null
+ * stream) or a hipStream_t.  Tip states start as "unknown", pattern weights as 1, the
+ * category rates as 1 and the category weights as 1/K. */
+int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes,
+              void* hip_stream, hp_instance** out);
+int hp_destroy(hp_instance* inst);
+int hp_set_stream(hp_instance* inst, void* hip_stream);
+
+/* Copy the message of the last failed call on inst (or of hp_create if inst is NULL)
+ * into buf (always NUL-terminated when len > 0). */
+int hp_last_error(const hp_instance* inst, char* buf, size_t len);
+
+#define HP_Q_STATE_PAD      1
+#define HP_Q_PATTERN_PAD    2
+#define HP_Q_ELEMENT_BYTES  3
+#define HP_Q_BLOCKS         4  /* pattern tiles (workgroups) one traversal launches   */
+#define HP_Q_RUNTIME_VERSION 5 /* hipRuntimeGetVersion() of the runtime in use        */
+int hp_query(const hp_instance* inst, int what, int64_t* out);
+
+/* ---------------------------------------------------------------- data */
+
+/* Tip states for one tip: states[n_patterns] with values 0..S-1, or S for unknown
+ * (all-ones partial).  on_device != 0: states is a device pointer (copied stream-ordered,
+ * not validated); otherwise a host pointer (validated, copied before return). */
+int hp_set_tip_states(hp_instance* inst, int tip, const uint8_t* states, int on_device);
+/* Pattern weights c_p >= 0 (host, FP64, n_patterns values; non-integers allowed). */
+int hp_set_pattern_weights(hp_instance* inst, const double* weights);
+/* Stationary frequencies of slot idx (host, FP64, S values, > 0, summing to 1 +- 1e-9). */
+int hp_set_frequencies(hp_instance* inst, int idx, const double* pi);
+/* Rate-category rates r_k >= 0 and weights w_k >= 0 (host FP64, K values each). */
+int hp_set_category_rates(hp_instance* inst, const double* rates);
+int hp_set_category_weights(hp_instance* inst, const double* weights);
+/* Eigensystem of slot idx: row-major S x S V and Vinv with Q = V diag(lam) Vinv (host FP64).
+ * The library also forms Q itself in FP64, for the gradient. */
+int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv,
+                 const double* lam);
+
+/* ---------------------------------------------------------------- transition matrices */
+
+/* For i < count: matrix slot mat_idx[i] <- P_k(t[i]) = V diag(exp(lam r_k t[i])) Vinv for
+ * every category k, computed in FP64 and stored in the instance precision.  t: host FP64,
+ * finite and >= 0 (HP_ERR_VALUE otherwise). */
+int hp_update_matrices(hp_instance* inst, int eigen_idx, const int32_t* mat_idx,
+                       const double* t, int count);
+
+/* ---------------------------------------------------------------- traversals */
+
+/* Post-order partial updates, in list order (children must be computed before use). */
+int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count);
+
+/* Root integration of post buffer root_buf with frequency slot freq_idx:
+ *   l_p = ln(sum_k w_k sum_x pi_x post[k,p,x]) + E_p ln 2 ,  lnL = sum_p c_p l_p  (FP64).
+ * Blocking: writes *out_lnl and, if out_site_lnl != NULL, n_patterns values (host).
+ * Returns HP_ERR_NUMERIC (and lnL = -inf) if some weighted site likelihood is 0 or
+ * not finite. */
+int hp_root_lnl(hp_instance* inst, int root_buf, int freq_idx, double* out_lnl,
+                double* out_site_lnl);
+
+/* Pre-order partial updates (no gradients), in list order (parents before children). */
+int hp_update_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx);
+
+/* Pre-order partial updates fused with the branch-length gradients of the model whose
+ * rate matrix comes from eigen slot eigen_idx: for every child c with gradX >= 0,
+ *   out_grad[gradX] = sum_p c_p [sum_k w_k r_k pre_c^T Q post_c] / [sum_k w_k pre_c^T post_c]
+ * Blocking; out_grad is host memory of n_grad FP64 values, slots not named by the list
+ * are set to 0. */
+int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx,
+                     int eigen_idx, double* out_grad, int n_grad);
+
+/* ---------------------------------------------------------------- whole-tree evaluation */
+
+/* Fix the tree used by hp_evaluate*: children[2N-1][2] (row-major int32) in the standard
+ * numbering (tips 0..N-1, internal N..2N-2, root 2N-2; tips have -1 children).  Internal
+ * node v uses post buffer v and pre buffer v-N; branch c (the edge above node c) uses
+ * matrix slot c and gradient slot c.  Builds and uploads the operation lists and the
+ * rescaling plan once. */
+int hp_set_tree(hp_instance* inst, const int32_t* children);
+
+/* Host-only: the operation lists hp_set_tree builds for a children table, for inspection or
+ * for driving the operation-level calls.  out_post_ops receives N-1 hp_post_op (post-order,
+ * children first, with the rescale flags of the given policy) and out_pre_ops N-1 hp_pre_op
+ * (parents first).  Touches no device; the error message is read with hp_last_error(NULL). */
+int hp_plan_tree(int n_tips, const int32_t* children, int scaling, int scale_period,
+                 int32_t* out_post_ops, int32_t* out_pre_ops);
+
+/* One full evaluation on the tree of hp_set_tree with model slot 0: transition matrices
+ * for all 2N-2 branches from t (FP64, 2N-2 values, indexed by node), post-order partials,
+ * root integration, and, if want_grad, pre-order partials and all 2N-2 branch gradients.
+ * Host pointers; blocking.  grad may be NULL when want_grad == 0. */
+int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_lnl,
+                double* out_grad);
+
+/* The same evaluation, fully stream-ordered: d_t (2N-2 FP64 branch lengths), d_out
+ * (1 + 2N-2 FP64: lnL then gradients) are device pointers; nothing is synchronised.
+ * Branch lengths are validated on the device: a negative or non-finite length makes the
+ * output NaN and raises the status word read by hp_status (HP_ERR_VALUE). */
+int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, double* d_out);
+
+/* Synchronise the stream and return (then clear) the device-side status of work enqueued
+ * since the last call: HP_OK, HP_ERR_VALUE or HP_ERR_NUMERIC. */
+int hp_status(hp_instance* inst);
+
+/* ---------------------------------------------------------------- kernel timing
+ * The paper measures the time spent inside the library.  While enabled, every kernel an
+ * instance launches is bracketed by HIP events on its stream (a few microseconds of
+ * overhead per launch).  hp_profile_read synchronises the stream and returns, per kernel
+ * class, the summed milliseconds and launch counts since the last read, then resets them. */
+#define HP_KERNEL_PMAT       0  /* transition-matrix assembly                          */
+#define HP_KERNEL_TRAVERSAL  1  /* post-/pre-order partials, root and gradient sums    */
+#define HP_KERNEL_REDUCE     2  /* second stage of the pattern reductions              */
+#define HP_KERNEL_CLASSES    3
+int hp_profile(hp_instance* inst, int enable);
+int hp_profile_read(hp_instance* inst, double* out_ms, int64_t* out_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIPPHYLO_H */

@@ -1,0 +1,822 @@
+// Host runtime behind the C ABI of include/hipphylo.h: descriptor validation, workspace
+// layout, input validation and upload, the tree scheduler (operation lists and the
+// rescaling plan) and kernel dispatch.  The library allocates no device memory: every
+// device region is carved from the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hp_internal.h"
+
+using hp::Instance;
+using hp::Layout;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(Instance* I, int code, const std::string& msg) {
+    if (I) I->err = msg; else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(Instance* I, hipError_t e, const char* what) {
+    return fail(I, HP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HP_HIP(I, expr)                                        \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail((I), e_, #expr); \
+    } while (0)
+
+// Switch to the instance's device for the duration of a call, then restore.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int check_desc(const hp_desc* d) {
+    if (!d) return fail(nullptr, HP_ERR_ARG, "descriptor is NULL");
+    if (d->n_tips < 2) return fail(nullptr, HP_ERR_ARG, "n_tips must be >= 2");
+    if (d->n_patterns < 1) return fail(nullptr, HP_ERR_ARG, "n_patterns must be >= 1");
+    if (d->n_states < 2 || d->n_states > hp::kMaxStates)
+        return fail(nullptr, HP_ERR_UNSUPPORTED, "n_states must be in [2, 64]");
+    if (d->n_categories < 1 || d->n_categories > hp::kMaxCategories)
+        return fail(nullptr, HP_ERR_UNSUPPORTED, "n_categories must be in [1, 8]");
+    if (d->n_partials < 1 || d->n_matrices < 1 || d->n_eigen < 1)
+        return fail(nullptr, HP_ERR_ARG, "n_partials, n_matrices and n_eigen must be >= 1");
+    if (d->precision < HP_PREC_F64 || d->precision > HP_PREC_F16)
+        return fail(nullptr, HP_ERR_ARG, "unknown precision");
+    if (d->scaling < HP_SCALE_NONE || d->scaling > HP_SCALE_EVERY_K_LEVELS)
+        return fail(nullptr, HP_ERR_ARG, "unknown scaling policy");
+    if (d->scaling == HP_SCALE_EVERY_K_LEVELS && d->scale_period < 1)
+        return fail(nullptr, HP_ERR_ARG, "scale_period must be >= 1");
+    const bool lowp = d->precision == HP_PREC_BF16 || d->precision == HP_PREC_F16;
+    if (lowp && d->n_states <= 4)
+        return fail(nullptr, HP_ERR_UNSUPPORTED,
+                    "BF16/FP16 matrix-core partials are for S > 4 (amino-acid and codon models)");
+    // guard the int32 index arithmetic inside kernels
+    const double pad_p = std::ceil(d->n_patterns / 64.0) * 64.0;
+    if (pad_p * d->n_categories * 64.0 > 2.0e9)
+        return fail(nullptr, HP_ERR_UNSUPPORTED, "n_patterns * n_categories too large for one instance");
+    return HP_OK;
+}
+
+int max_grad_slots(const hp_desc& d) {
+    return std::max(d.n_matrices, 2 * d.n_tips - 2);
+}
+
+int max_ops(const hp_desc& d) { return 4 * std::max(d.n_partials, d.n_tips) + 4; }
+
+}  // namespace
+
+namespace hp {
+
+int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_out, Layout* L) {
+    const int S = d.n_states, K = d.n_categories;
+    const bool lowp = d.precision == HP_PREC_BF16 || d.precision == HP_PREC_F16;
+    int S_pad;
+    if (S <= 4) S_pad = 4;
+    else if (lowp) S_pad = S <= 32 ? 32 : 64;
+    else S_pad = (S + 3) / 4 * 4;
+    const int P_pad = (d.n_patterns + kWave - 1) / kWave * kWave;
+    const int elem = d.precision == HP_PREC_F64 ? 8 : d.precision == HP_PREC_F32 ? 4 : 2;
+    const int celem = d.precision == HP_PREC_F64 ? 8 : 4;  // matrices / Q / freqs: FP64 or FP32
+    const size_t np = (size_t)d.n_partials, nm = (size_t)d.n_matrices, ne = (size_t)d.n_eigen;
+    const int n_blocks = P_pad / kWave;
+    Layout l{};
+    l.post_stride = (size_t)K * P_pad * S_pad;
+    l.mat_stride = (size_t)K * S_pad * S_pad;
+    l.tip_stride = (size_t)K * (S + 1) * S_pad;
+    l.eig_stride = (size_t)2 * S * S + S;
+    l.max_out = 1 + max_grad_slots(d);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    l.tips = take((size_t)d.n_tips * P_pad);
+    l.pweights = take((size_t)P_pad * 8);
+    l.post = take(np * l.post_stride * elem);
+    l.post_exp = take(np * P_pad * 4);
+    l.pre = take(np * l.post_stride * elem);
+    // matrices: FP64/FP32 copies always; low precision adds packed MFMA operands after them
+    size_t mats_bytes = nm * l.mat_stride * celem;
+    if (lowp) mats_bytes += nm * l.mat_stride * 2 * 2;  // P and P^T in 16-bit
+    l.mats = take(mats_bytes);
+    l.tiptab = take(nm * l.tip_stride * celem);
+    l.eig = take(ne * l.eig_stride * 8);
+    l.Qc = take(ne * S_pad * S_pad * celem);
+    l.freq_c = take(ne * S_pad * celem);
+    l.freq_d = take(ne * S_pad * 8);
+    l.cat_d = take(2 * kMaxCategories * 8);
+    l.t_stage = take(nm * 8);
+    l.idx_stage = take(nm * 4);
+    l.ops_stage = take((size_t)max_ops(d) * kPreOpInts * 4);
+    l.tree_ops = take((size_t)(d.n_tips) * (kPostOpInts + kPreOpInts) * 4);
+    l.partials = take((size_t)l.max_out * n_blocks * 8);
+    l.results = take((size_t)l.max_out * 8);
+    l.status = take(64);
+    l.site = take((size_t)P_pad * 8);
+    l.total = off;
+    *S_pad_out = S_pad;
+    *P_pad_out = P_pad;
+    *elem_out = elem;
+    *L = l;
+    return HP_OK;
+}
+
+}  // namespace hp
+
+namespace {
+
+// Synchronous upload of a borrowed host array (the call returns only once it is consumed).
+int upload(Instance* I, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return HP_OK;
+    HP_HIP(I, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, I->stream));
+    HP_HIP(I, hipStreamSynchronize(I->stream));
+    return HP_OK;
+}
+
+template <typename T>
+void store_compute(std::vector<unsigned char>& buf, const std::vector<double>& v) {
+    buf.resize(v.size() * sizeof(T));
+    T* p = reinterpret_cast<T*>(buf.data());
+    for (size_t i = 0; i < v.size(); ++i) p[i] = T(v[i]);
+}
+
+// Upload FP64 host values converted to the compute type (FP64 for F64, FP32 otherwise).
+int upload_compute(Instance* I, size_t off, const std::vector<double>& v) {
+    std::vector<unsigned char> buf;
+    if (I->d.precision == HP_PREC_F64) store_compute<double>(buf, v);
+    else store_compute<float>(buf, v);
+    return upload(I, I->ws + off, buf.data(), buf.size());
+}
+
+int read_status(Instance* I, int32_t* out) {
+    HP_HIP(I, hipMemcpyAsync(I->host_status, I->at<int32_t>(I->L.status), 4, hipMemcpyDeviceToHost,
+                             I->stream));
+    HP_HIP(I, hipStreamSynchronize(I->stream));
+    *out = *I->host_status;
+    if (*out) HP_HIP(I, hp::launch_fill_i32(*I, I->at<int32_t>(I->L.status), 0, 1));
+    return HP_OK;
+}
+
+// ---- kernel timing: events bracket every launch on the instance stream while enabled
+constexpr size_t kProfPairs = 4096;
+
+int prof_flush(Instance* I) {
+    hp::Profiler& P = I->prof;
+    if (P.used == 0) return HP_OK;
+    HP_HIP(I, hipStreamSynchronize(I->stream));
+    for (size_t i = 0; i < P.used; ++i) {
+        float ms = 0.f;
+        HP_HIP(I, hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]));
+        P.ms[P.kind[i]] += ms;
+        P.count[P.kind[i]] += 1;
+    }
+    P.used = 0;
+    return HP_OK;
+}
+
+// Launch `fn` (returning hipError_t) bracketed by timing events when profiling is on.
+template <typename F>
+hipError_t timed(Instance* I, int kind, F&& fn) {
+    hp::Profiler& P = I->prof;
+    if (!P.on) return fn();
+    if (P.used == kProfPairs && prof_flush(I) != HP_OK) return hipErrorUnknown;
+    hipError_t e = hipEventRecord(P.ev[2 * P.used], I->stream);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(P.ev[2 * P.used + 1], I->stream);
+    if (e != hipSuccess) return e;
+    P.kind[P.used++] = kind;
+    return hipSuccess;
+}
+
+#define HP_PMAT(...) timed(I, hp::kPmat, [&] { return hp::launch_pmat(__VA_ARGS__); })
+#define HP_WALK(...) timed(I, hp::kTraversal, [&] { return hp::launch_walk(__VA_ARGS__); })
+#define HP_REDUCE(...) timed(I, hp::kReduce, [&] { return hp::launch_reduce(__VA_ARGS__); })
+
+bool finite_all(const double* v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+int check_post_buf(Instance* I, int b, const char* what) {
+    if (b < I->d.n_tips || b >= I->d.n_tips + I->d.n_partials)
+        return fail(I, HP_ERR_INDEX, std::string(what) + " is not a post-order buffer index");
+    return HP_OK;
+}
+
+int check_child(Instance* I, int c, const char* what) {
+    if (c < 0 || c >= I->d.n_tips + I->d.n_partials)
+        return fail(I, HP_ERR_INDEX, std::string(what) + " out of range");
+    return HP_OK;
+}
+
+int check_mat(Instance* I, int m) {
+    if (m < 0 || m >= I->d.n_matrices) return fail(I, HP_ERR_INDEX, "matrix index out of range");
+    return HP_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+int hp_workspace_bytes(const hp_desc* desc, size_t* out_bytes) {
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!out_bytes) return fail(nullptr, HP_ERR_ARG, "out_bytes is NULL");
+    int S_pad, P_pad, elem;
+    Layout L;
+    hp::compute_layout(*desc, &S_pad, &P_pad, &elem, &L);
+    *out_bytes = L.total;
+    return HP_OK;
+}
+
+int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+              hp_instance** out) {
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!out) return fail(nullptr, HP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!dev_workspace) return fail(nullptr, HP_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+        return fail(nullptr, HP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    auto* I = new Instance();
+    I->d = *desc;
+    hp::compute_layout(*desc, &I->S_pad, &I->P_pad, &I->elem, &I->L);
+    if (workspace_bytes < I->L.total) {
+        delete I;
+        return fail(nullptr, HP_ERR_WORKSPACE, "workspace smaller than hp_workspace_bytes");
+    }
+    I->n_blocks = I->P_pad / hp::kWave;
+    I->ws = static_cast<uint8_t*>(dev_workspace);
+    I->ws_bytes = workspace_bytes;
+    I->stream = static_cast<hipStream_t>(hip_stream);
+    I->eigen_set.assign(desc->n_eigen, 0);
+    I->freq_set.assign(desc->n_eigen, 0);
+    DeviceGuard g(desc->device);
+    auto cleanup = [&](int code) {
+        std::string m = I->err;
+        if (I->host_out) (void)hipHostFree(I->host_out);
+        if (I->host_status) (void)hipHostFree(I->host_status);
+        delete I;
+        g_create_error = m;
+        return code;
+    };
+    if (!g.ok) return cleanup(fail(I, HP_ERR_DEVICE, "hipSetDevice failed"));
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dev_workspace) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != desc->device) {
+        (void)hipGetLastError();
+        return cleanup(fail(I, HP_ERR_WORKSPACE, "workspace is not device memory on desc->device"));
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&I->host_out), (size_t)I->L.max_out * 8) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&I->host_status), 64) != hipSuccess)
+        return cleanup(fail(I, HP_ERR_DEVICE, "hipHostMalloc of the result staging buffer failed"));
+    const int S = desc->n_states, K = desc->n_categories;
+    // tips unknown everywhere (padding patterns stay unknown for ever), weights 1 / 0 (padding)
+    if (hp::launch_fill_u8(*I, I->at<uint8_t>(I->L.tips), (uint8_t)S, (size_t)desc->n_tips * I->P_pad) ||
+        hp::launch_fill_f64(*I, I->at<double>(I->L.pweights), 1.0, desc->n_patterns) ||
+        hp::launch_fill_f64(*I, I->at<double>(I->L.pweights) + desc->n_patterns, 0.0,
+                            I->P_pad - desc->n_patterns) ||
+        hp::launch_fill_i32(*I, I->at<int32_t>(I->L.status), 0, 16))
+        return cleanup(fail(I, HP_ERR_DEVICE, "initialising the workspace failed"));
+    std::vector<double> cat(2 * hp::kMaxCategories, 0.0);
+    for (int k = 0; k < K; ++k) {
+        cat[k] = 1.0;
+        cat[hp::kMaxCategories + k] = 1.0 / K;
+    }
+    if (upload(I, I->ws + I->L.cat_d, cat.data(), cat.size() * 8)) return cleanup(HP_ERR_DEVICE);
+    *out = reinterpret_cast<hp_instance*>(I);
+    return HP_OK;
+}
+
+int hp_destroy(hp_instance* inst) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    {
+        DeviceGuard g(I->d.device);
+        (void)hipStreamSynchronize(I->stream);
+        for (hipEvent_t e : I->prof.ev) (void)hipEventDestroy(e);
+        if (I->host_out) (void)hipHostFree(I->host_out);
+        if (I->host_status) (void)hipHostFree(I->host_status);
+    }
+    delete I;
+    return HP_OK;
+}
+
+int hp_set_stream(hp_instance* inst, void* hip_stream) {
+    if (!inst) return HP_ERR_ARG;
+    reinterpret_cast<Instance*>(inst)->stream = static_cast<hipStream_t>(hip_stream);
+    return HP_OK;
+}
+
+int hp_last_error(const hp_instance* inst, char* buf, size_t len) {
+    if (!buf || len == 0) return HP_ERR_ARG;
+    const std::string& m = inst ? reinterpret_cast<const Instance*>(inst)->err : g_create_error;
+    std::snprintf(buf, len, "%s", m.c_str());
+    return HP_OK;
+}
+
+int hp_query(const hp_instance* inst, int what, int64_t* out) {
+    if (!inst || !out) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<const Instance*>(inst);
+    switch (what) {
+        case HP_Q_STATE_PAD: *out = I->S_pad; return HP_OK;
+        case HP_Q_PATTERN_PAD: *out = I->P_pad; return HP_OK;
+        case HP_Q_ELEMENT_BYTES: *out = I->elem; return HP_OK;
+        case HP_Q_BLOCKS: *out = I->n_blocks; return HP_OK;
+        case HP_Q_RUNTIME_VERSION: {
+            int v = 0;
+            if (hipRuntimeGetVersion(&v) != hipSuccess) return HP_ERR_DEVICE;
+            *out = v;
+            return HP_OK;
+        }
+        default: return HP_ERR_ARG;
+    }
+}
+
+int hp_set_tip_states(hp_instance* inst, int tip, const uint8_t* states, int on_device) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!states) return fail(I, HP_ERR_ARG, "states is NULL");
+    if (tip < 0 || tip >= I->d.n_tips) return fail(I, HP_ERR_INDEX, "tip index out of range");
+    DeviceGuard g(I->d.device);
+    uint8_t* dst = I->at<uint8_t>(I->L.tips) + (size_t)tip * I->P_pad;
+    if (on_device) {
+        HP_HIP(I, hipMemcpyAsync(dst, states, I->d.n_patterns, hipMemcpyDeviceToDevice, I->stream));
+        return HP_OK;
+    }
+    for (int p = 0; p < I->d.n_patterns; ++p)
+        if (states[p] > I->d.n_states) return fail(I, HP_ERR_VALUE, "tip state > n_states");
+    return upload(I, dst, states, I->d.n_patterns);
+}
+
+int hp_set_pattern_weights(hp_instance* inst, const double* w) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!w) return fail(I, HP_ERR_ARG, "weights is NULL");
+    for (int p = 0; p < I->d.n_patterns; ++p)
+        if (!(w[p] >= 0.0) || !std::isfinite(w[p])) return fail(I, HP_ERR_VALUE, "pattern weight < 0 or not finite");
+    DeviceGuard g(I->d.device);
+    return upload(I, I->ws + I->L.pweights, w, (size_t)I->d.n_patterns * 8);
+}
+
+int hp_set_frequencies(hp_instance* inst, int idx, const double* pi) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!pi) return fail(I, HP_ERR_ARG, "frequencies are NULL");
+    if (idx < 0 || idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "frequency slot out of range");
+    double s = 0.0;
+    for (int x = 0; x < I->d.n_states; ++x) {
+        if (!(pi[x] >= 0.0) || !std::isfinite(pi[x])) return fail(I, HP_ERR_VALUE, "frequency < 0 or not finite");
+        s += pi[x];
+    }
+    if (std::fabs(s - 1.0) > 1e-9) return fail(I, HP_ERR_VALUE, "frequencies do not sum to 1");
+    DeviceGuard g(I->d.device);
+    std::vector<double> v(I->S_pad, 0.0);
+    std::copy(pi, pi + I->d.n_states, v.begin());
+    int rc = upload(I, I->ws + I->L.freq_d + (size_t)idx * I->S_pad * 8, v.data(), v.size() * 8);
+    if (rc) return rc;
+    rc = upload_compute(I, I->L.freq_c + (size_t)idx * I->S_pad * (I->d.precision == HP_PREC_F64 ? 8 : 4), v);
+    if (rc) return rc;
+    I->freq_set[idx] = 1;
+    return HP_OK;
+}
+
+static int set_cat(hp_instance* inst, const double* v, int which) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!v) return fail(I, HP_ERR_ARG, "category array is NULL");
+    for (int k = 0; k < I->d.n_categories; ++k)
+        if (!(v[k] >= 0.0) || !std::isfinite(v[k])) return fail(I, HP_ERR_VALUE, "category value < 0 or not finite");
+    DeviceGuard g(I->d.device);
+    return upload(I, I->ws + I->L.cat_d + (size_t)which * hp::kMaxCategories * 8, v,
+                  (size_t)I->d.n_categories * 8);
+}
+
+int hp_set_category_rates(hp_instance* inst, const double* r) { return set_cat(inst, r, 0); }
+int hp_set_category_weights(hp_instance* inst, const double* w) { return set_cat(inst, w, 1); }
+
+int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv, const double* lam) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!V || !Vinv || !lam) return fail(I, HP_ERR_ARG, "eigensystem array is NULL");
+    if (idx < 0 || idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "eigen slot out of range");
+    const int S = I->d.n_states, Sp = I->S_pad;
+    if (!finite_all(V, (size_t)S * S) || !finite_all(Vinv, (size_t)S * S) || !finite_all(lam, S))
+        return fail(I, HP_ERR_VALUE, "eigensystem is not finite");
+    std::vector<double> e((size_t)2 * S * S + S);
+    std::copy(V, V + S * S, e.begin());
+    std::copy(Vinv, Vinv + S * S, e.begin() + S * S);
+    std::copy(lam, lam + S, e.begin() + 2 * S * S);
+    // Q = V diag(lam) Vinv in FP64, for the gradient sandwich
+    std::vector<double> Q((size_t)Sp * Sp, 0.0);
+    for (int x = 0; x < S; ++x)
+        for (int y = 0; y < S; ++y) {
+            double s = 0.0;
+            for (int j = 0; j < S; ++j) s += V[x * S + j] * lam[j] * Vinv[j * S + y];
+            Q[(size_t)x * Sp + y] = s;
+        }
+    DeviceGuard g(I->d.device);
+    int rc = upload(I, I->ws + I->L.eig + (size_t)idx * I->L.eig_stride * 8, e.data(), e.size() * 8);
+    if (rc) return rc;
+    rc = upload_compute(I, I->L.Qc + (size_t)idx * Sp * Sp * (I->d.precision == HP_PREC_F64 ? 8 : 4), Q);
+    if (rc) return rc;
+    I->eigen_set[idx] = 1;
+    return HP_OK;
+}
+
+int hp_update_matrices(hp_instance* inst, int eigen_idx, const int32_t* mat_idx, const double* t, int count) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (count < 0 || count > I->d.n_matrices) return fail(I, HP_ERR_ARG, "bad matrix count");
+    if (count == 0) return HP_OK;
+    if (!mat_idx || !t) return fail(I, HP_ERR_ARG, "mat_idx or t is NULL");
+    if (eigen_idx < 0 || eigen_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "eigen slot out of range");
+    if (!I->eigen_set[eigen_idx]) return fail(I, HP_ERR_STATE, "eigensystem not set");
+    for (int i = 0; i < count; ++i) {
+        int rc = check_mat(I, mat_idx[i]);
+        if (rc) return rc;
+        if (!(t[i] >= 0.0) || !std::isfinite(t[i])) return fail(I, HP_ERR_VALUE, "branch length < 0 or not finite");
+    }
+    DeviceGuard g(I->d.device);
+    int rc = upload(I, I->ws + I->L.idx_stage, mat_idx, (size_t)count * 4);
+    if (rc) return rc;
+    rc = upload(I, I->ws + I->L.t_stage, t, (size_t)count * 8);
+    if (rc) return rc;
+    HP_HIP(I, HP_PMAT(*I, eigen_idx, I->at<int32_t>(I->L.idx_stage), I->at<double>(I->L.t_stage), count));
+    return HP_OK;
+}
+
+int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (count < 0 || count > max_ops(I->d)) return fail(I, HP_ERR_ARG, "bad operation count");
+    if (count == 0) return HP_OK;
+    if (!ops) return fail(I, HP_ERR_ARG, "ops is NULL");
+    for (int i = 0; i < count; ++i) {
+        const hp_post_op& o = ops[i];
+        int rc = check_post_buf(I, o.dest, "dest");
+        if (!rc) rc = check_child(I, o.child1, "child1");
+        if (!rc) rc = check_child(I, o.child2, "child2");
+        if (!rc) rc = check_mat(I, o.mat1);
+        if (!rc) rc = check_mat(I, o.mat2);
+        if (rc) return rc;
+        if (o.rescale != 0 && o.rescale != 1) return fail(I, HP_ERR_ARG, "rescale must be 0 or 1");
+    }
+    DeviceGuard g(I->d.device);
+    int rc = upload(I, I->ws + I->L.ops_stage, ops, (size_t)count * sizeof(hp_post_op));
+    if (rc) return rc;
+    hp::WalkArgs a;
+    a.mode = hp::kPost;
+    a.post_ops = I->at<int32_t>(I->L.ops_stage);
+    a.n_post = count;
+    HP_HIP(I, HP_WALK(*I, a));
+    return HP_OK;
+}
+
+int hp_root_lnl(hp_instance* inst, int root_buf, int freq_idx, double* out_lnl, double* out_site) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!out_lnl) return fail(I, HP_ERR_ARG, "out_lnl is NULL");
+    int rc = check_post_buf(I, root_buf, "root_buf");
+    if (rc) return rc;
+    if (freq_idx < 0 || freq_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "frequency slot out of range");
+    if (!I->freq_set[freq_idx]) return fail(I, HP_ERR_STATE, "frequencies not set");
+    DeviceGuard g(I->d.device);
+    hp::WalkArgs a;
+    a.mode = hp::kRootBuf;
+    a.root_buf = root_buf;
+    a.freq_idx = freq_idx;
+    a.site = out_site ? I->at<double>(I->L.site) : nullptr;
+    HP_HIP(I, HP_WALK(*I, a));
+    HP_HIP(I, HP_REDUCE(*I, 1, I->at<double>(I->L.results)));
+    HP_HIP(I, hipMemcpyAsync(I->host_out, I->at<double>(I->L.results), 8, hipMemcpyDeviceToHost, I->stream));
+    if (out_site)
+        HP_HIP(I, hipMemcpyAsync(out_site, I->at<double>(I->L.site), (size_t)I->d.n_patterns * 8,
+                                 hipMemcpyDeviceToHost, I->stream));
+    HP_HIP(I, hipStreamSynchronize(I->stream));
+    *out_lnl = I->host_out[0];
+    int32_t st = 0;
+    rc = read_status(I, &st);
+    if (rc) return rc;
+    if (st & hp::kStatusNumeric) {
+        *out_lnl = -INFINITY;
+        return fail(I, HP_ERR_NUMERIC, "a site likelihood was zero or not finite");
+    }
+    if (st & hp::kStatusValue) return fail(I, HP_ERR_VALUE, "an invalid branch length reached the device");
+    return HP_OK;
+}
+
+// Gradient slots are checked only when gradients are requested (n_grad >= 0); the
+// partials-only call ignores them.
+static int check_pre_ops(Instance* I, const hp_pre_op* ops, int count, int n_grad) {
+    std::vector<char> seen(std::max(n_grad, 0), 0);
+    for (int i = 0; i < count; ++i) {
+        const hp_pre_op& o = ops[i];
+        if (o.parent_pre >= I->d.n_partials) return fail(I, HP_ERR_INDEX, "parent_pre out of range");
+        int rc = check_child(I, o.child1_post, "child1_post");
+        if (!rc) rc = check_child(I, o.child2_post, "child2_post");
+        if (!rc) rc = check_mat(I, o.mat1);
+        if (!rc) rc = check_mat(I, o.mat2);
+        if (rc) return rc;
+        if (o.child1_pre >= I->d.n_partials || o.child2_pre >= I->d.n_partials)
+            return fail(I, HP_ERR_INDEX, "child pre buffer out of range");
+        for (int g : {o.grad1, o.grad2}) {
+            if (g < 0 || n_grad < 0) continue;
+            if (g >= n_grad) return fail(I, HP_ERR_INDEX, "gradient slot >= n_grad");
+            if (seen[g]) return fail(I, HP_ERR_ARG, "gradient slot used twice");
+            seen[g] = 1;
+        }
+    }
+    return HP_OK;
+}
+
+static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int eigen_idx,
+                   double* out_grad, int n_grad, bool grad) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (count < 0 || count > max_ops(I->d)) return fail(I, HP_ERR_ARG, "bad operation count");
+    if (count > 0 && !ops) return fail(I, HP_ERR_ARG, "ops is NULL");
+    if (freq_idx < 0 || freq_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "frequency slot out of range");
+    if (!I->freq_set[freq_idx]) return fail(I, HP_ERR_STATE, "frequencies not set");
+    if (grad) {
+        if (!out_grad) return fail(I, HP_ERR_ARG, "out_grad is NULL");
+        if (n_grad < 0 || n_grad > max_grad_slots(I->d)) return fail(I, HP_ERR_ARG, "bad n_grad");
+        if (eigen_idx < 0 || eigen_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "eigen slot out of range");
+        if (!I->eigen_set[eigen_idx]) return fail(I, HP_ERR_STATE, "eigensystem not set");
+    }
+    int rc = check_pre_ops(I, ops, count, grad ? n_grad : -1);
+    if (rc) return rc;
+    DeviceGuard g(I->d.device);
+    if (count > 0) {
+        rc = upload(I, I->ws + I->L.ops_stage, ops, (size_t)count * sizeof(hp_pre_op));
+        if (rc) return rc;
+    }
+    hp::WalkArgs a;
+    a.mode = grad ? (hp::kPre | hp::kGrad) : hp::kPre;
+    a.pre_ops = I->at<int32_t>(I->L.ops_stage);
+    a.n_pre = count;
+    a.freq_idx = freq_idx;
+    a.eigen_idx = grad ? eigen_idx : 0;
+    a.n_grad = grad ? n_grad : 0;
+    HP_HIP(I, HP_WALK(*I, a));
+    if (!grad) return HP_OK;
+    HP_HIP(I, HP_REDUCE(*I, 1 + n_grad, I->at<double>(I->L.results)));
+    HP_HIP(I, hipMemcpyAsync(I->host_out, I->at<double>(I->L.results), (size_t)(1 + n_grad) * 8,
+                             hipMemcpyDeviceToHost, I->stream));
+    HP_HIP(I, hipStreamSynchronize(I->stream));
+    std::copy(I->host_out + 1, I->host_out + 1 + n_grad, out_grad);
+    return HP_OK;
+}
+
+int hp_update_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx) {
+    return run_pre(inst, ops, count, freq_idx, 0, nullptr, 0, false);
+}
+
+int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int eigen_idx,
+                     double* out_grad, int n_grad) {
+    return run_pre(inst, ops, count, freq_idx, eigen_idx, out_grad, n_grad, true);
+}
+
+// ------------------------------------------------------------------ whole-tree evaluation
+
+// Validate a children table and build the operation lists used for a whole-tree
+// evaluation: post-order by depth-first search from the root (children before parents),
+// the rescaling plan, and the pre-order list (parents before children).  Host only.
+static int plan_tree(Instance* I, int N, const int32_t* children, int scaling, int period,
+                     std::vector<int32_t>* post, std::vector<int32_t>* pre) {
+    const int root = 2 * N - 2, n_nodes = 2 * N - 1;
+    std::vector<int> parent(n_nodes, -1);
+    for (int v = 0; v < n_nodes; ++v) {
+        const int a = children[2 * v], b = children[2 * v + 1];
+        if (v < N) {
+            if (a != -1 || b != -1) return fail(I, HP_ERR_ARG, "a tip has children");
+            continue;
+        }
+        if (a < 0 || a >= n_nodes || b < 0 || b >= n_nodes || a == b || a == root || b == root)
+            return fail(I, HP_ERR_INDEX, "bad child index");
+        if (parent[a] != -1 || parent[b] != -1) return fail(I, HP_ERR_ARG, "a node has two parents");
+        parent[a] = v;
+        parent[b] = v;
+    }
+    for (int v = 0; v < n_nodes; ++v)
+        if (v != root && parent[v] == -1) return fail(I, HP_ERR_ARG, "a node has no parent");
+    // every node must be reached exactly once from the root (no cycles)
+    std::vector<int> order;
+    order.reserve(N - 1);
+    std::vector<char> visited(n_nodes, 0);
+    std::vector<std::pair<int, bool>> stack{{root, false}};
+    int reached = 0;
+    while (!stack.empty()) {
+        auto [v, done] = stack.back();
+        stack.pop_back();
+        if (done) {
+            order.push_back(v);
+            continue;
+        }
+        if (visited[v]) return fail(I, HP_ERR_ARG, "the children table is not a tree");
+        visited[v] = 1;
+        ++reached;
+        if (v < N) continue;
+        stack.push_back({v, true});
+        stack.push_back({children[2 * v + 1], false});
+        stack.push_back({children[2 * v], false});
+    }
+    if (reached != n_nodes) return fail(I, HP_ERR_ARG, "the children table is not a tree");
+    // rescaling plan: run = internal nodes combined since the last rescale on the longest
+    // path below; a node is rescaled when its run reaches the period
+    std::vector<int> run(n_nodes, 0);
+    post->clear();
+    pre->clear();
+    post->reserve((size_t)(N - 1) * hp::kPostOpInts);
+    pre->reserve((size_t)(N - 1) * hp::kPreOpInts);
+    for (int v : order) {
+        const int a = children[2 * v], b = children[2 * v + 1];
+        const int r = 1 + std::max(run[a], run[b]);
+        int resc = 0;
+        if (scaling == HP_SCALE_EVERY_NODE) resc = 1;
+        else if (scaling == HP_SCALE_EVERY_K_LEVELS && r >= period) resc = 1;
+        run[v] = resc ? 0 : r;
+        post->insert(post->end(), {v, a, a, b, b, resc});
+    }
+    for (auto it = order.rbegin(); it != order.rend(); ++it) {
+        const int v = *it;
+        const int a = children[2 * v], b = children[2 * v + 1];
+        pre->insert(pre->end(), {v == root ? -1 : v - N, a, a, a >= N ? a - N : -1, a, b, b,
+                                 b >= N ? b - N : -1, b});
+    }
+    return HP_OK;
+}
+
+int hp_plan_tree(int n_tips, const int32_t* children, int scaling, int scale_period,
+                 int32_t* out_post_ops, int32_t* out_pre_ops) {
+    if (n_tips < 2 || !children || !out_post_ops || !out_pre_ops)
+        return fail(nullptr, HP_ERR_ARG, "bad argument");
+    if (scaling < HP_SCALE_NONE || scaling > HP_SCALE_EVERY_K_LEVELS ||
+        (scaling == HP_SCALE_EVERY_K_LEVELS && scale_period < 1))
+        return fail(nullptr, HP_ERR_ARG, "bad scaling policy");
+    std::vector<int32_t> post, pre;
+    int rc = plan_tree(nullptr, n_tips, children, scaling, scale_period, &post, &pre);
+    if (rc) return rc;
+    std::copy(post.begin(), post.end(), out_post_ops);
+    std::copy(pre.begin(), pre.end(), out_pre_ops);
+    return HP_OK;
+}
+
+int hp_set_tree(hp_instance* inst, const int32_t* children) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!children) return fail(I, HP_ERR_ARG, "children is NULL");
+    const int N = I->d.n_tips;
+    if (I->d.n_partials < N - 1) return fail(I, HP_ERR_ARG, "n_partials < n_tips - 1");
+    if (I->d.n_matrices < 2 * N - 2) return fail(I, HP_ERR_ARG, "n_matrices < 2 n_tips - 2");
+    std::vector<int32_t> post, pre;
+    int rc = plan_tree(I, N, children, I->d.scaling, I->d.scale_period, &post, &pre);
+    if (rc) return rc;
+    DeviceGuard g(I->d.device);
+    int32_t* dst = I->at<int32_t>(I->L.tree_ops);
+    rc = upload(I, dst, post.data(), post.size() * 4);
+    if (rc) return rc;
+    rc = upload(I, dst + (size_t)(N - 1) * hp::kPostOpInts, pre.data(), pre.size() * 4);
+    if (rc) return rc;
+    I->tree_set = true;
+    I->tree_n_post = N - 1;
+    I->tree_n_pre = N - 1;
+    return HP_OK;
+}
+
+static int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out) {
+    const int N = I->d.n_tips;
+    HP_HIP(I, HP_PMAT(*I, 0, nullptr, d_t, 2 * N - 2));
+    hp::WalkArgs a;
+    a.mode = want_grad ? (hp::kPost | hp::kRootFused | hp::kPre | hp::kGrad) : (hp::kPost | hp::kRootFused);
+    a.post_ops = I->at<int32_t>(I->L.tree_ops);
+    a.n_post = I->tree_n_post;
+    a.pre_ops = a.post_ops + (size_t)(N - 1) * hp::kPostOpInts;
+    a.n_pre = want_grad ? I->tree_n_pre : 0;
+    a.n_grad = want_grad ? 2 * N - 2 : 0;
+    HP_HIP(I, HP_WALK(*I, a));
+    HP_HIP(I, HP_REDUCE(*I, 1 + a.n_grad, d_out));
+    return HP_OK;
+}
+
+static int check_eval_state(Instance* I) {
+    if (!I->tree_set) return fail(I, HP_ERR_STATE, "hp_set_tree was not called");
+    if (!I->eigen_set[0]) return fail(I, HP_ERR_STATE, "eigensystem 0 not set");
+    if (!I->freq_set[0]) return fail(I, HP_ERR_STATE, "frequencies 0 not set");
+    return HP_OK;
+}
+
+int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_lnl, double* out_grad) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!t || !out_lnl || (want_grad && !out_grad)) return fail(I, HP_ERR_ARG, "NULL argument");
+    int rc = check_eval_state(I);
+    if (rc) return rc;
+    const int nb = 2 * I->d.n_tips - 2;
+    for (int c = 0; c < nb; ++c)
+        if (!(t[c] >= 0.0) || !std::isfinite(t[c])) return fail(I, HP_ERR_VALUE, "branch length < 0 or not finite");
+    DeviceGuard g(I->d.device);
+    rc = upload(I, I->ws + I->L.t_stage, t, (size_t)nb * 8);
+    if (rc) return rc;
+    double* d_out = I->at<double>(I->L.results);
+    rc = enqueue_evaluate(I, I->at<double>(I->L.t_stage), want_grad, d_out);
+    if (rc) return rc;
+    const int n_out = want_grad ? 1 + nb : 1;
+    HP_HIP(I, hipMemcpyAsync(I->host_out, d_out, (size_t)n_out * 8, hipMemcpyDeviceToHost, I->stream));
+    HP_HIP(I, hipStreamSynchronize(I->stream));
+    *out_lnl = I->host_out[0];
+    if (want_grad) std::copy(I->host_out + 1, I->host_out + n_out, out_grad);
+    int32_t st = 0;
+    rc = read_status(I, &st);
+    if (rc) return rc;
+    if (st & hp::kStatusNumeric) {
+        *out_lnl = -INFINITY;
+        return fail(I, HP_ERR_NUMERIC, "a site likelihood was zero or not finite");
+    }
+    return HP_OK;
+}
+
+int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, double* d_out) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!d_t || !d_out) return fail(I, HP_ERR_ARG, "NULL argument");
+    int rc = check_eval_state(I);
+    if (rc) return rc;
+    DeviceGuard g(I->d.device);
+    return enqueue_evaluate(I, d_t, want_grad, d_out);
+}
+
+int hp_profile(hp_instance* inst, int enable) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    DeviceGuard g(I->d.device);
+    hp::Profiler& P = I->prof;
+    if (enable && P.ev.empty()) {
+        P.ev.resize(2 * kProfPairs);
+        P.kind.resize(kProfPairs);
+        for (auto& e : P.ev) HP_HIP(I, hipEventCreate(&e));
+    }
+    if (!enable) {
+        int rc = prof_flush(I);
+        if (rc) return rc;
+    }
+    P.on = enable != 0;
+    return HP_OK;
+}
+
+int hp_profile_read(hp_instance* inst, double* out_ms, int64_t* out_count) {
+    if (!inst || !out_ms || !out_count) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    DeviceGuard g(I->d.device);
+    int rc = prof_flush(I);
+    if (rc) return rc;
+    hp::Profiler& P = I->prof;
+    for (int k = 0; k < hp::kNumClasses; ++k) {
+        out_ms[k] = P.ms[k];
+        out_count[k] = P.count[k];
+        P.ms[k] = 0.0;
+        P.count[k] = 0;
+    }
+    return HP_OK;
+}
+
+int hp_status(hp_instance* inst) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    DeviceGuard g(I->d.device);
+    int32_t st = 0;
+    int rc = read_status(I, &st);
+    if (rc) return rc;
+    if (st & hp::kStatusValue) return fail(I, HP_ERR_VALUE, "an invalid branch length reached the device");
+    if (st & hp::kStatusNumeric) return fail(I, HP_ERR_NUMERIC, "a site likelihood was zero or not finite");
+    return HP_OK;
+}
+
+}  // extern "C"

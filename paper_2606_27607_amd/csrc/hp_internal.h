@@ -1,0 +1,99 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hipphylo.h"
+
+namespace hp {
+
+constexpr int kWave = 64;          // CDNA wavefront width: one lane per pattern
+constexpr int kMaxCategories = 8;
+constexpr int kMaxStates = 64;
+constexpr int kPostOpInts = 6;     // hp_post_op
+constexpr int kPreOpInts = 9;      // hp_pre_op
+
+// Device status bits (hp_status).
+constexpr int kStatusValue = 1;    // invalid branch length seen by the matrix kernel
+constexpr int kStatusNumeric = 2;  // zero / non-finite site likelihood
+
+// Traversal kernel modes (bit set).
+enum WalkMode : int {
+    kPost = 1,        // walk the post-order list, storing every destination
+    kRootFused = 2,   // the last post op is the root: integrate it instead of storing it
+    kRootBuf = 4,     // integrate a stored post buffer (no post walk)
+    kPre = 8,         // walk the pre-order list
+    kGrad = 16,       // accumulate branch gradients during the pre-order walk
+};
+
+struct Layout {
+    // byte offsets into the workspace
+    size_t tips, pweights, post, post_exp, pre, mats, tiptab, eig, Qc, freq_c, freq_d, cat_d,
+        t_stage, idx_stage, ops_stage, tree_ops, partials, results, status, site, total;
+    size_t post_stride;   // elements per partial buffer (K * P_pad * S_pad)
+    size_t mat_stride;    // elements per matrix slot (K * S_pad * S_pad)
+    size_t tip_stride;    // elements per tip-table slot (K * (S+1) * S_pad)
+    size_t eig_stride;    // doubles per eigen slot (2 S^2 + S)
+    int max_out;          // output slots per reduction row (1 + max gradients)
+};
+
+// Kernel classes timed by hp_profile.
+enum KernelClass : int { kPmat = 0, kTraversal = 1, kReduce = 2, kNumClasses = 3 };
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // pairs (begin, end)
+    std::vector<int> kind;
+    size_t used = 0;
+    double ms[kNumClasses] = {};
+    int64_t count[kNumClasses] = {};
+};
+
+struct Instance {
+    hp_desc d{};
+    int S_pad = 0, P_pad = 0, elem = 0, n_blocks = 0;
+    hipStream_t stream = nullptr;
+    uint8_t* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L{};
+    std::string err;
+    std::vector<char> eigen_set, freq_set;
+    bool tree_set = false;
+    int tree_n_post = 0, tree_n_pre = 0;
+    double* host_out = nullptr;     // pinned host buffer for results
+    int32_t* host_status = nullptr; // pinned
+    Profiler prof;
+
+    template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+// Layout computation shared by hp_workspace_bytes and hp_create.
+int compute_layout(const hp_desc& d, int* S_pad, int* P_pad, int* elem, Layout* L);
+
+// ------------------------------------------------------------------ launchers
+// All return hipSuccess or the first HIP error.
+hipError_t launch_pmat(const Instance& I, int eigen_idx, const int32_t* d_idx, const double* d_t,
+                       int count);
+struct WalkArgs {
+    int mode = 0;
+    const int32_t* post_ops = nullptr;
+    int n_post = 0;
+    const int32_t* pre_ops = nullptr;
+    int n_pre = 0;
+    int root_buf = -1;     // kRootBuf: post buffer index (>= n_tips)
+    int freq_idx = 0;
+    int eigen_idx = 0;
+    int n_grad = 0;        // gradient slots; reduction rows hold 1 + n_grad values
+    double* site = nullptr;
+};
+hipError_t launch_walk(const Instance& I, const WalkArgs& a);
+hipError_t launch_reduce(const Instance& I, int n_out, double* d_out);
+hipError_t launch_fill_i32(const Instance& I, int32_t* p, int32_t v, size_t n);
+hipError_t launch_fill_u8(const Instance& I, uint8_t* p, uint8_t v, size_t n);
+hipError_t launch_fill_f64(const Instance& I, double* p, double v, size_t n);
+
+}  // namespace hp

@@ -1,0 +1,337 @@
+// Traversal kernels for small state spaces (S <= 4, padded to 4): nucleotide models.
+//
+// Work decomposition.  A workgroup owns 64 consecutive site patterns and has one
+// wavefront per rate category (K waves).  Lane = pattern, wave = category, so
+// every partial-likelihood load or store of a wave is one contiguous 1 KiB (FP32)
+// or 2 KiB (FP64) run of the [category][pattern][state] layout, and the
+// transition matrix P_k of an edge is uniform across the wave: it is read with
+// scalar loads and used directly as SGPR operands of the FMAs.  Because site
+// patterns are conditionally independent, a workgroup walks the whole operation
+// list for its own patterns without any grid-wide synchronisation; only the
+// per-pattern rescaling exponent and the category sums of the gradient cross
+// waves, through LDS.
+//
+// Pattern sums (lnL and every branch gradient) are two-stage: each workgroup
+// writes one FP64 partial per output slot ([slot][workgroup] layout), and
+// reduce_rows sums each slot over workgroups in a fixed order, so results are
+// bitwise reproducible whatever else runs on the device.
+#include <climits>
+
+#include "hp_internal.h"
+
+namespace hp {
+namespace {
+
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+// Reinterpret a pointer to device memory that is read-only for the whole kernel
+// as a constant-address-space pointer: uniform reads then compile to scalar loads.
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)p;
+}
+
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+    T x, y, z, w;
+};
+
+template <typename T>
+__device__ __forceinline__ V4<T> ld4(const T* p) {
+    return *reinterpret_cast<const V4<T>*>(p);
+}
+template <typename T>
+__device__ __forceinline__ V4<T> ld4(cptr<T> p) {
+    return {p[0], p[1], p[2], p[3]};
+}
+template <typename T>
+__device__ __forceinline__ void st4(T* p, const V4<T>& v) {
+    *reinterpret_cast<V4<T>*>(p) = v;
+}
+template <typename T>
+__device__ __forceinline__ V4<T> mul(const V4<T>& a, const V4<T>& b) {
+    return {a.x * b.x, a.y * b.y, a.z * b.z, a.w * b.w};
+}
+template <typename T>
+__device__ __forceinline__ T dot(const V4<T>& a, const V4<T>& b) {
+    return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+}
+// u = P v with P row-major 4x4 (row = from-state).
+template <typename T>
+__device__ __forceinline__ V4<T> matvec(cptr<T> P, const V4<T>& v) {
+    return {P[0] * v.x + P[1] * v.y + P[2] * v.z + P[3] * v.w,
+            P[4] * v.x + P[5] * v.y + P[6] * v.z + P[7] * v.w,
+            P[8] * v.x + P[9] * v.y + P[10] * v.z + P[11] * v.w,
+            P[12] * v.x + P[13] * v.y + P[14] * v.z + P[15] * v.w};
+}
+// u = P^T v.
+template <typename T>
+__device__ __forceinline__ V4<T> mattvec(cptr<T> P, const V4<T>& v) {
+    return {P[0] * v.x + P[4] * v.y + P[8] * v.z + P[12] * v.w,
+            P[1] * v.x + P[5] * v.y + P[9] * v.z + P[13] * v.w,
+            P[2] * v.x + P[6] * v.y + P[10] * v.z + P[14] * v.w,
+            P[3] * v.x + P[7] * v.y + P[11] * v.z + P[15] * v.w};
+}
+template <typename T>
+__device__ __forceinline__ T max4(const V4<T>& a) {
+    return fmax(fmax(a.x, a.y), fmax(a.z, a.w));
+}
+
+__device__ __forceinline__ int frexp_exp(float v) { return __builtin_amdgcn_frexp_expf(v); }
+__device__ __forceinline__ int frexp_exp(double v) { return __builtin_amdgcn_frexp_exp(v); }
+__device__ __forceinline__ float ldexp_(float v, int e) { return __builtin_amdgcn_ldexpf(v, e); }
+__device__ __forceinline__ double ldexp_(double v, int e) { return __builtin_amdgcn_ldexp(v, e); }
+
+// Binary exponent of a positive maximum; INT_MIN for zero / NaN so that a category that
+// underflowed to zero never decides the pattern's scale.
+template <typename T>
+__device__ __forceinline__ int scale_exp(T m) {
+    return (m > T(0)) ? frexp_exp(m) : INT_MIN;
+}
+template <typename T>
+__device__ __forceinline__ V4<T> ldexp4(const V4<T>& a, int e) {
+    return {ldexp_(a.x, e), ldexp_(a.y, e), ldexp_(a.z, e), ldexp_(a.w, e)};
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <typename T>
+struct WalkDev {
+    const uint8_t* tips;    // [N][P_pad]
+    const double* pw;       // [P_pad]
+    T* post;                // [n_partials][K][P_pad][4]
+    int32_t* pexp;          // [n_partials][P_pad]
+    T* pre;                 // [n_partials][K][P_pad][4]
+    const T* mats;          // [n_mat][K][4][4]
+    const T* tiptab;        // [n_mat][K][S+1][4]
+    const T* Q;             // [4][4]
+    const T* freq;          // [4]
+    const double* cat_r;    // [K]
+    const double* cat_w;    // [K]
+    const int32_t* post_ops;
+    const int32_t* pre_ops;
+    double* site;           // [P_pad] or null
+    double* partials;       // [n_out][n_blocks]
+    int32_t* status;
+    size_t stride;          // elements per partial buffer
+    int n_post, n_pre, root_buf, n_out, n_blocks;
+    int N, P_pad, K, S, rescale_pre;
+};
+
+template <typename T>
+__device__ __forceinline__ V4<T> child_u(const WalkDev<T>& a, int c, int m, int k, int p) {
+    if (c < a.N) {
+        int s = a.tips[(size_t)c * a.P_pad + p];
+        s = s > a.S ? a.S : s;
+        return ld4(a.tiptab + ((size_t)(m * a.K + k) * (a.S + 1) + s) * 4);
+    }
+    V4<T> v = ld4(a.post + (size_t)(c - a.N) * a.stride + ((size_t)k * a.P_pad + p) * 4);
+    return matvec(as_const(a.mats + (size_t)(m * a.K + k) * 16), v);
+}
+
+template <typename T>
+__device__ __forceinline__ int child_exp(const WalkDev<T>& a, int c, int p) {
+    return c < a.N ? 0 : a.pexp[(size_t)(c - a.N) * a.P_pad + p];
+}
+
+template <typename T, int KMAX, int MODE>
+__global__ void __launch_bounds__(KMAX * kWave) walk_small(const WalkDev<T> a) {
+    __shared__ int sh_e[2][2][KMAX][kWave];
+    __shared__ T sh_v[2][3][KMAX][kWave];
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int p = blockIdx.x * kWave + lane;
+    const int K = a.K;
+    int sb = 0;  // exchange counter: consecutive LDS exchanges alternate buffers
+
+    if (MODE & (kRootFused | kRootBuf | kGrad)) {
+        for (int j = threadIdx.x; j < a.n_out; j += blockDim.x)
+            a.partials[(size_t)j * a.n_blocks + blockIdx.x] = 0.0;
+        __syncthreads();
+    }
+
+    auto integrate_root = [&](const V4<T>& x, int E) {
+        const int s = (sb++) & 1;
+        sh_v[s][0][k][lane] = T(as_const(a.cat_w)[k]) * dot(ld4(as_const(a.freq)), x);
+        __syncthreads();
+        if (k == 0) {
+            double L = 0.0;
+            for (int kk = 0; kk < K; ++kk) L += double(sh_v[s][0][kk][lane]);
+            double l = log(L) + double(E) * 0.69314718055994530942;
+            if (!(L > 0.0) || !isfinite(l)) {
+                atomicOr(a.status, kStatusNumeric);
+                l = -INFINITY;
+            }
+            if (a.site) a.site[p] = l;
+            const double w = a.pw[p];
+            double tot = wave_sum(w == 0.0 ? 0.0 : w * l);
+            if (lane == 0) a.partials[blockIdx.x] = tot;
+        }
+    };
+
+    if (MODE & kPost) {
+        for (int i = 0; i < a.n_post; ++i) {
+            cptr<int32_t> op = as_const(a.post_ops + (size_t)i * kPostOpInts);
+            const int dest = op[0], c1 = op[1], m1 = op[2], c2 = op[3], m2 = op[4], resc = op[5];
+            V4<T> x = mul(child_u(a, c1, m1, k, p), child_u(a, c2, m2, k, p));
+            int E = child_exp(a, c1, p) + child_exp(a, c2, p);
+            if (resc) {
+                const int s = (sb++) & 1;
+                sh_e[s][0][k][lane] = scale_exp(max4(x));
+                __syncthreads();
+                int em = sh_e[s][0][0][lane];
+                for (int kk = 1; kk < K; ++kk) em = max(em, sh_e[s][0][kk][lane]);
+                em = (em == INT_MIN) ? 0 : em;
+                x = ldexp4(x, -em);
+                E += em;
+            }
+            if ((MODE & kRootFused) && i == a.n_post - 1) {
+                integrate_root(x, E);
+            } else {
+                st4(a.post + (size_t)(dest - a.N) * a.stride + ((size_t)k * a.P_pad + p) * 4, x);
+                if (k == 0) a.pexp[(size_t)(dest - a.N) * a.P_pad + p] = E;
+            }
+        }
+    }
+
+    if (MODE & kRootBuf) {
+        const V4<T> x =
+            ld4(a.post + (size_t)(a.root_buf - a.N) * a.stride + ((size_t)k * a.P_pad + p) * 4);
+        integrate_root(x, a.pexp[(size_t)(a.root_buf - a.N) * a.P_pad + p]);
+    }
+
+    if (MODE & kPre) {
+        const T wk = T(as_const(a.cat_w)[k]);
+        const T wrk = T(as_const(a.cat_w)[k] * as_const(a.cat_r)[k]);
+        const double cp = a.pw[p];
+        const int wave_b = K > 1 ? 1 : 0;
+        for (int j = 0; j < a.n_pre; ++j) {
+            cptr<int32_t> op = as_const(a.pre_ops + (size_t)j * kPreOpInts);
+            const int pp = op[0];
+            const int c1 = op[1], m1 = op[2], q1 = op[3], g1 = op[4];
+            const int c2 = op[5], m2 = op[6], q2 = op[7], g2 = op[8];
+            const V4<T> qn = pp < 0 ? ld4(as_const(a.freq))
+                                    : ld4(a.pre + (size_t)pp * a.stride + ((size_t)k * a.P_pad + p) * 4);
+            const V4<T> ua = child_u(a, c1, m1, k, p);
+            const V4<T> ub = child_u(a, c2, m2, k, p);
+            const V4<T> va = mul(qn, ub);
+            const V4<T> vb = mul(qn, ua);
+            V4<T> qa{}, qb{};
+            int ea = INT_MIN, eb = INT_MIN;
+            if (q1 >= 0) {
+                qa = mattvec(as_const(a.mats + (size_t)(m1 * K + k) * 16), va);
+                if (a.rescale_pre) ea = scale_exp(max4(qa));
+            }
+            if (q2 >= 0) {
+                qb = mattvec(as_const(a.mats + (size_t)(m2 * K + k) * 16), vb);
+                if (a.rescale_pre) eb = scale_exp(max4(qb));
+            }
+            const bool grad = (MODE & kGrad) && (g1 >= 0 || g2 >= 0);
+            const bool resc = a.rescale_pre && (q1 >= 0 || q2 >= 0);
+            if (grad || resc) {
+                const int s = (sb++) & 1;
+                if (resc) {
+                    sh_e[s][0][k][lane] = ea;
+                    sh_e[s][1][k][lane] = eb;
+                }
+                if (grad) {
+                    cptr<T> Qp = as_const(a.Q);
+                    sh_v[s][0][k][lane] = wk * dot(va, ua);  // = w_k pre_c^T post_c, same for both
+                    sh_v[s][1][k][lane] = g1 >= 0 ? wrk * dot(va, matvec(Qp, ua)) : T(0);
+                    sh_v[s][2][k][lane] = g2 >= 0 ? wrk * dot(vb, matvec(Qp, ub)) : T(0);
+                }
+                __syncthreads();
+                if (resc) {
+                    ea = sh_e[s][0][0][lane];
+                    eb = sh_e[s][1][0][lane];
+                    for (int kk = 1; kk < K; ++kk) {
+                        ea = max(ea, sh_e[s][0][kk][lane]);
+                        eb = max(eb, sh_e[s][1][kk][lane]);
+                    }
+                }
+                if (grad) {
+                    // wave 0 finishes child 1's gradient, wave 1 (or 0 if K == 1) child 2's
+                    for (int side = 0; side < 2; ++side) {
+                        const int g = side ? g2 : g1;
+                        if (g < 0 || k != (side ? wave_b : 0)) continue;
+                        double den = 0.0, num = 0.0;
+                        for (int kk = 0; kk < K; ++kk) {
+                            den += double(sh_v[s][0][kk][lane]);
+                            num += double(sh_v[s][1 + side][kk][lane]);
+                        }
+                        const double tot = wave_sum(cp == 0.0 ? 0.0 : cp * (num / den));
+                        if (lane == 0) a.partials[(size_t)(1 + g) * a.n_blocks + blockIdx.x] = tot;
+                    }
+                }
+            }
+            ea = (ea == INT_MIN) ? 0 : ea;
+            eb = (eb == INT_MIN) ? 0 : eb;
+            if (q1 >= 0)
+                st4(a.pre + (size_t)q1 * a.stride + ((size_t)k * a.P_pad + p) * 4, ldexp4(qa, -ea));
+            if (q2 >= 0)
+                st4(a.pre + (size_t)q2 * a.stride + ((size_t)k * a.P_pad + p) * 4, ldexp4(qb, -eb));
+        }
+    }
+}
+
+template <typename T, int KMAX>
+hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
+    const Layout& L = I.L;
+    WalkDev<T> a{};
+    a.tips = I.at<uint8_t>(L.tips);
+    a.pw = I.at<double>(L.pweights);
+    a.post = I.at<T>(L.post);
+    a.pexp = I.at<int32_t>(L.post_exp);
+    a.pre = I.at<T>(L.pre);
+    a.mats = I.at<T>(L.mats);
+    a.tiptab = I.at<T>(L.tiptab);
+    a.Q = I.at<T>(L.Qc) + (size_t)w.eigen_idx * I.S_pad * I.S_pad;
+    a.freq = I.at<T>(L.freq_c) + (size_t)w.freq_idx * I.S_pad;
+    a.cat_r = I.at<double>(L.cat_d);
+    a.cat_w = I.at<double>(L.cat_d) + kMaxCategories;
+    a.post_ops = w.post_ops;
+    a.pre_ops = w.pre_ops;
+    a.site = w.site;
+    a.partials = I.at<double>(L.partials);
+    a.status = I.at<int32_t>(L.status);
+    a.stride = L.post_stride;
+    a.n_post = w.n_post;
+    a.n_pre = w.n_pre;
+    a.root_buf = w.root_buf;
+    a.n_out = 1 + w.n_grad;
+    a.n_blocks = I.n_blocks;
+    a.N = I.d.n_tips;
+    a.P_pad = I.P_pad;
+    a.K = I.d.n_categories;
+    a.S = I.d.n_states;
+    a.rescale_pre = I.d.scaling != HP_SCALE_NONE;
+    dim3 grid(I.n_blocks), block(kWave * I.d.n_categories);
+#define HP_LAUNCH(M) hipLaunchKernelGGL((walk_small<T, KMAX, M>), grid, block, 0, I.stream, a)
+    switch (w.mode) {
+        case kPost: HP_LAUNCH(kPost); break;
+        case kPost | kRootFused: HP_LAUNCH(kPost | kRootFused); break;
+        case kRootBuf: HP_LAUNCH(kRootBuf); break;
+        case kPre: HP_LAUNCH(kPre); break;
+        case kPre | kGrad: HP_LAUNCH(kPre | kGrad); break;
+        case kPost | kRootFused | kPre | kGrad: HP_LAUNCH(kPost | kRootFused | kPre | kGrad); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef HP_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_walk_small(const Instance& I, const WalkArgs& w) {
+    const bool f64 = I.d.precision == HP_PREC_F64;
+    if (I.d.n_categories <= 4)
+        return f64 ? dispatch_walk<double, 4>(I, w) : dispatch_walk<float, 4>(I, w);
+    return f64 ? dispatch_walk<double, 8>(I, w) : dispatch_walk<float, 8>(I, w);
+}
+
+}  // namespace hp

@@ -60,6 +60,17 @@ def normalise_rate(Q: np.ndarray, pi: np.ndarray) -> np.ndarray:
     return Q / mu
 
 
+def reversible(R, pi) -> np.ndarray:
+    """Normalised reversible rate matrix from a symmetric exchangeability matrix R."""
+    pi = np.asarray(pi, dtype=np.float64)
+    return normalise_rate(_reversible(R, pi), pi)
+
+
+def binary(pi) -> np.ndarray:
+    """Two-state reversible model (used for state counts below four)."""
+    return reversible(np.array([[0.0, 1.0], [1.0, 0.0]]), pi)
+
+
 def jc69() -> tuple[np.ndarray, np.ndarray]:
     pi = np.full(4, 0.25)
     R = np.ones((4, 4))

@@ -64,6 +64,14 @@ class Workload:
 def _model(kind: str, rng: np.random.Generator, **kw):
     if kind == "jc69":
         return models.jc69()
+    if kind == "bin":
+        pi = rng.dirichlet(np.full(2, 10.0))
+        return models.binary(pi), pi
+    if kind == "three":
+        pi = rng.dirichlet(np.full(3, 10.0))
+        R = np.zeros((3, 3))
+        R[np.triu_indices(3, 1)] = rng.gamma(2.0, 1.0, size=3)
+        return models.reversible(R + R.T, pi), pi
     if kind == "hky":
         pi = rng.dirichlet(np.full(4, 10.0))
         return models.hky85(kw.get("kappa", 2.0), pi), pi

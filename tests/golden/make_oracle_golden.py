@@ -1,0 +1,50 @@
+"""Write full-size FP64 oracle results for the named workloads (calls only oracle/ and synth/).
+
+    python tests/golden/make_oracle_golden.py nuc8 nuc128 ...
+
+Each tests/golden/oracle_<name>.json holds the log-likelihood, every branch gradient and
+the site log-likelihoods of a fixed sample of patterns (every (P // 509)-th pattern plus
+the last one, so the ragged tail of the pattern padding is covered).  The GPU parity tests
+compare the library's full-size results with these values; nothing here comes from the
+GPU path.
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+
+def sample_indices(n_patterns: int) -> np.ndarray:
+    step = max(1, n_patterns // 509)
+    idx = np.arange(0, n_patterns, step)
+    return np.unique(np.concatenate([idx, [n_patterns - 1]]))
+
+
+def main(names):
+    for name in names:
+        t0 = time.time()
+        wl = synth.config_workload(name)
+        lnl, site, grad = oracle.lnl_and_grad(wl.tree.children, wl.n_tips, wl.t, wl.Q, wl.pi,
+                                              wl.rates, wl.cat_weights, wl.tips, wl.weights,
+                                              chunk=10000 if wl.n_states > 4 else 20000)
+        idx = sample_indices(wl.n_patterns)
+        out = {"workload": name, "n_tips": wl.n_tips, "n_patterns": wl.n_patterns,
+               "n_states": wl.n_states, "seed": wl.meta["seed"], "lnl": lnl,
+               "grad": grad.tolist(), "site_idx": idx.tolist(), "site_lnl": site[idx].tolist(),
+               "oracle_seconds": time.time() - t0}
+        with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as f:
+            json.dump(out, f)
+        print(f"{name}: lnL {lnl:.6f} in {time.time() - t0:.1f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["nuc8", "nuc128", "codon64", "nuc256", "codon32"])

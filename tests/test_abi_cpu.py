@@ -1,0 +1,162 @@
+"""CPU checks of the C ABI: the library loads and exports every function include/hipphylo.h
+declares; descriptor validation and workspace sizing; the host-only tree planner."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2606_27607_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hipphylo.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^int\s+(hp_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_and_library_exports_every_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, f"binding lacks {n}"
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_header_compiles_as_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "hipphylo.h"\nint main(void){hp_desc d={0}; (void)d; return HP_OK;}\n')
+    r = os.system(f"gcc -std=c99 -Wall -Werror -I {ROOT}/include -c {src} -o {tmp_path}/t.o")
+    assert r == 0
+
+
+def desc(**kw):
+    base = dict(n_tips=128, n_patterns=100000, n_states=4, n_categories=4, n_partials=127,
+                n_matrices=254, n_eigen=1, precision=1, scaling=2, scale_period=4, device=0)
+    base.update(kw)
+    return _lib.hp_desc(**base)
+
+
+def ws_bytes(lib, d):
+    n = ctypes.c_size_t()
+    rc = lib.hp_workspace_bytes(ctypes.byref(d), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_sizing(lib):
+    rc, n = ws_bytes(lib, desc())
+    assert rc == 0
+    # post + pre partials dominate: 2 * 127 * K * P_pad * S_pad * 4 bytes
+    partials = 2 * 127 * 4 * 100032 * 4 * 4
+    assert partials < n < partials * 1.1
+    assert n % 256 == 0
+    rc64, n64 = ws_bytes(lib, desc(precision=0))
+    assert rc64 == 0 and n64 > 1.9 * partials
+    rcb, nb = ws_bytes(lib, desc(n_states=61, precision=2))
+    assert rcb == 0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n_tips", 1, _lib.HP_ERR_ARG), ("n_patterns", 0, _lib.HP_ERR_ARG),
+    ("n_states", 65, _lib.HP_ERR_UNSUPPORTED), ("n_states", 1, _lib.HP_ERR_UNSUPPORTED),
+    ("n_categories", 9, _lib.HP_ERR_UNSUPPORTED), ("precision", 7, _lib.HP_ERR_ARG),
+    ("scaling", 5, _lib.HP_ERR_ARG), ("scale_period", 0, _lib.HP_ERR_ARG),
+    ("n_matrices", 0, _lib.HP_ERR_ARG),
+])
+def test_descriptor_validation(lib, field, value, code):
+    rc, _ = ws_bytes(lib, desc(**{field: value}))
+    assert rc == code
+    msg = _lib.last_error(lib, None)
+    assert msg
+
+
+def test_low_precision_needs_large_state_space(lib):
+    rc, _ = ws_bytes(lib, desc(precision=2, n_states=4))
+    assert rc == _lib.HP_ERR_UNSUPPORTED
+
+
+def test_create_rejects_bad_workspace(lib):
+    d = desc(n_tips=4, n_patterns=10, n_partials=3, n_matrices=6)
+    inst = ctypes.c_void_p()
+    assert lib.hp_create(ctypes.byref(d), None, 0, None, ctypes.byref(inst)) == _lib.HP_ERR_WORKSPACE
+    assert lib.hp_create(ctypes.byref(d), ctypes.c_void_p(257), 1 << 20, None,
+                         ctypes.byref(inst)) == _lib.HP_ERR_WORKSPACE
+    assert "256" in _lib.last_error(lib, None)
+
+
+def plan(lib, tree, scaling=2, period=4):
+    N = tree.n_tips
+    post = np.zeros((N - 1, 6), dtype=np.int32)
+    pre = np.zeros((N - 1, 9), dtype=np.int32)
+    ch = np.ascontiguousarray(tree.children.astype(np.int32))
+    rc = lib.hp_plan_tree(N, ctypes.c_void_p(ch.ctypes.data), scaling, period,
+                          ctypes.c_void_p(post.ctypes.data), ctypes.c_void_p(pre.ctypes.data))
+    return rc, post, pre
+
+
+@pytest.mark.parametrize("maker", ["yule", "cat", "bal"])
+@pytest.mark.parametrize("period", [1, 2, 4, 7])
+def test_plan_tree_orders_and_rescaling(lib, maker, period):
+    N = 57
+    tree = {"yule": synth.yule_tree(N, np.random.default_rng(3)), "cat": synth.caterpillar_tree(N),
+            "bal": synth.balanced_tree(N)}[maker]
+    rc, post, pre = plan(lib, tree, 2, period)
+    assert rc == 0
+    done = set(range(N))
+    for dest, c1, m1, c2, m2, resc in post:
+        assert c1 in done and c2 in done and m1 == c1 and m2 == c2   # children first
+        assert {c1, c2} == set(tree.children[dest])
+        done.add(dest)
+    assert post[-1][0] == tree.root
+    # every root-to-tip path meets a rescaled node at least every `period` internal nodes
+    resc = {int(r[0]): int(r[5]) for r in post}
+    for tip in range(N):
+        run, v = 0, int(tree.parent[tip])
+        while v != -1:
+            run = 0 if resc[v] else run + 1
+            assert run < period
+            v = int(tree.parent[v])
+    # pre-order: parents before children, root first with parent_pre -1
+    assert pre[0][0] == -1
+    have = {tree.root}
+    for row in pre:
+        parent = tree.root if row[0] < 0 else row[0] + N
+        assert parent in have
+        for post_c, mat, pre_c, g in (row[1:5], row[5:9]):
+            assert mat == post_c == g
+            assert pre_c == (post_c - N if post_c >= N else -1)
+            have.add(int(post_c))
+    assert len(have) == 2 * N - 1
+
+
+def test_plan_tree_policies(lib):
+    tree = synth.yule_tree(20, np.random.default_rng(1))
+    assert (plan(lib, tree, 0)[1][:, 5] == 0).all()
+    assert (plan(lib, tree, 1)[1][:, 5] == 1).all()
+    assert (plan(lib, tree, 2, 1)[1][:, 5] == 1).all()
+
+
+def test_plan_tree_rejects_non_trees(lib):
+    tree = synth.yule_tree(6, np.random.default_rng(2))
+    ch = tree.children.copy()
+    ch[6, 0] = ch[7, 0]                                   # a node with two parents
+    rc, _, _ = plan(lib, synth.Tree(6, tree.parent, ch))
+    assert rc in (_lib.HP_ERR_ARG, _lib.HP_ERR_INDEX)
+    ch = tree.children.copy()
+    ch[0, 0] = 1                                           # a tip with children
+    assert plan(lib, synth.Tree(6, tree.parent, ch))[0] == _lib.HP_ERR_ARG
+    ch = tree.children.copy()
+    ch[6, 1] = 10                                          # the root as a child
+    assert plan(lib, synth.Tree(6, tree.parent, ch))[0] in (_lib.HP_ERR_ARG, _lib.HP_ERR_INDEX)

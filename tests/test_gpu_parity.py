@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances: FP64 on the GPU agrees with the oracle to rounding (1e-12 relative on lnL,
+1e-11 of the largest gradient); FP32 meets the 1e-5 relative lnL bound and its gradient
+error is bounded at 1e-3 of the largest gradient (the derivation is in the design notes:
+per-pattern FP32 ratios carry ~1e-6 relative error and the branch gradient is a sum of
+terms of both signs).
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import (announce, golden, grad_err, make_instance, oracle_eval, post_ops, pre_ops,
+                         rel)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+# --------------------------------------------------------------- whole-tree evaluation
+
+def test_nuc8_fp64_full_config():
+    wl = synth.config_workload("nuc8")
+    inst = make_instance(wl, "f64", "none")
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    assert rel(lnl, lnl_o) < 1e-12
+    assert grad_err(g, g_o) < 1e-11
+    gold = golden("nuc8")
+    if gold:
+        assert rel(lnl, gold["lnl"]) < 1e-12
+        assert grad_err(g, np.array(gold["grad"])) < 1e-11
+
+
+@pytest.mark.parametrize("precision,scaling,period", [("f64", "every_node", 1), ("f64", "every_k", 3),
+                                                      ("f32", "every_k", 4), ("f32", "every_node", 1)])
+@pytest.mark.parametrize("kind,n,npat,seed", [("gtr", 24, 1000, 1), ("hky", 9, 300, 2),
+                                              ("gtr", 2, 77, 3), ("gtr", 60, 65, 4)])
+def test_evaluate_matches_oracle(precision, scaling, period, kind, n, npat, seed):
+    wl = synth.make_workload(kind, n, npat, seed=seed, unknown_frac=0.05)
+    inst = make_instance(wl, precision, scaling, period)
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    if precision == "f64":
+        assert rel(lnl, lnl_o) < 1e-12 and grad_err(g, g_o) < 1e-11
+    else:
+        assert rel(lnl, lnl_o) < 1e-5 and grad_err(g, g_o) < 1e-3
+    lnl_only = inst.evaluate(wl.t, want_grad=False)
+    assert lnl_only == lnl
+
+
+@pytest.mark.parametrize("K", [1, 3, 8])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_category_counts(K, precision):
+    wl = synth.make_workload("gtr", 13, 200, seed=K, n_categories=K)
+    inst = make_instance(wl, precision, "every_node")
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    tol = (1e-12, 1e-11) if precision == "f64" else (1e-5, 1e-3)
+    assert rel(lnl, lnl_o) < tol[0] and grad_err(g, g_o) < tol[1]
+
+
+@pytest.mark.parametrize("kind", ["bin", "three"])
+def test_fewer_than_four_states(kind):
+    wl = synth.make_workload(kind, 11, 130, seed=5, unknown_frac=0.1)
+    inst = make_instance(wl, "f64", "every_node")
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    assert rel(lnl, lnl_o) < 1e-12 and grad_err(g, g_o) < 1e-11
+
+
+def test_two_taxon_jc69_closed_form_on_gpu():
+    from pins import jc69_two_taxon
+    wl = synth.make_workload("jc69", 2, 16, seed=1, tree=synth.two_taxon_tree())
+    wl.t[:] = [0.13, 0.31, 0.0]
+    wl.tips = np.array([[a for a in range(4) for b in range(4)],
+                        [b for a in range(4) for b in range(4)]], dtype=np.uint8)
+    wl.weights = np.arange(1, 17, dtype=np.float64)
+    inst = make_instance(wl, "f64", "none")
+    lnl, g = inst.evaluate(wl.t)
+    Ls, Ld, gs, gd = jc69_two_taxon(0.44, wl.rates, wl.cat_weights)
+    same = wl.tips[0] == wl.tips[1]
+    assert rel(lnl, np.sum(wl.weights * np.where(same, np.log(Ls), np.log(Ld)))) < 1e-13
+    expect = np.sum(wl.weights * np.where(same, gs, gd))
+    assert np.allclose(g, [expect, expect], rtol=1e-12)
+
+
+def test_deep_caterpillar_needs_rescaling():
+    """A 300-taxon ladder: without rescaling FP32 partials underflow; with it lnL stays within
+    the FP32 tolerance."""
+    wl = synth.make_workload("gtr", 300, 200, seed=6, tree=synth.caterpillar_tree(300),
+                             branch_mean=0.1)
+    lnl_o, _, g_o = oracle_eval(wl)
+    inst = make_instance(wl, "f32", "every_k", 4)
+    lnl, g = inst.evaluate(wl.t)
+    assert rel(lnl, lnl_o) < 1e-5 and grad_err(g, g_o) < 1e-3
+    inst64 = make_instance(wl, "f64", "every_k", 8)
+    lnl64, g64 = inst64.evaluate(wl.t)
+    assert rel(lnl64, lnl_o) < 1e-12 and grad_err(g64, g_o) < 1e-10
+
+
+def test_single_pattern_and_zero_branch():
+    wl = synth.make_workload("hky", 7, 1, seed=7)
+    wl.t[3] = 0.0
+    inst = make_instance(wl, "f64", "every_node")
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    assert rel(lnl, lnl_o) < 1e-12 and grad_err(g, g_o) < 1e-11
+
+
+# --------------------------------------------------------------- operation-level API
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_op_level_api(precision):
+    wl = synth.make_workload("gtr", 17, 333, seed=8, unknown_frac=0.05)
+    inst = make_instance(wl, precision, "every_node", tree=False)
+    N = wl.n_tips
+    nb = 2 * N - 2
+    inst.update_matrices(np.arange(nb), wl.t[:nb])
+    inst.update_post(post_ops(wl.tree.children, N, rescale=1))
+    lnl, site = inst.root_lnl(2 * N - 2, site=True)
+    lnl_o, site_o, g_o = oracle_eval(wl)
+    tol = 1e-12 if precision == "f64" else 1e-5
+    assert rel(lnl, lnl_o) < tol
+    assert np.allclose(site, site_o, rtol=tol, atol=0)
+    g = inst.pre_gradients(pre_ops(wl.tree.children, N), nb)
+    assert grad_err(g, g_o) < (1e-11 if precision == "f64" else 1e-3)
+    # pre partials alone, then the same list again with gradients: same answer
+    inst.update_pre(pre_ops(wl.tree.children, N))
+    g2 = inst.pre_gradients(pre_ops(wl.tree.children, N), nb)
+    assert np.array_equal(g, g2)
+
+
+def test_partial_update_after_branch_change():
+    """Change one branch, recompute only the path to the root: lnL equals a full evaluation."""
+    wl = synth.make_workload("gtr", 20, 250, seed=9)
+    inst = make_instance(wl, "f64", "every_node", tree=False)
+    N = wl.n_tips
+    nb = 2 * N - 2
+    inst.update_matrices(np.arange(nb), wl.t[:nb])
+    ops = post_ops(wl.tree.children, N)
+    inst.update_post(ops)
+    c = 5
+    t2 = wl.t.copy()
+    t2[c] *= 1.7
+    inst.update_matrices([c], [t2[c]])
+    path, v = [], c
+    while v != 2 * N - 2:
+        v = int(wl.tree.parent[v])
+        path.append(v)
+    sub = np.array([o for o in ops if o[0] in path], dtype=np.int32)
+    inst.update_post(sub)
+    lnl = inst.root_lnl(2 * N - 2)
+    assert rel(lnl, oracle_eval(wl, t=t2, want_grad=False)[0]) < 1e-12
+
+
+# --------------------------------------------------------------- determinism
+
+def test_bitwise_repeatable_and_device_path():
+    import torch
+    wl = synth.make_workload("gtr", 40, 5000, seed=10)
+    inst = make_instance(wl, "f32", "every_k", 4)
+    a = inst.evaluate(wl.t)
+    b = inst.evaluate(wl.t)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+    t_dev = torch.tensor(wl.t[: 2 * wl.n_tips - 2], dtype=torch.float64, device="cuda")
+    out = inst.evaluate_device(t_dev)
+    inst.status()
+    o = out.cpu().numpy()
+    assert o[0] == a[0] and np.array_equal(o[1:], a[1])
+    # a second instance on another stream, interleaved: identical bits
+    inst2 = make_instance(wl, "f32", "every_k", 4)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out2 = inst2.evaluate_device(t_dev)
+    out1 = inst.evaluate_device(t_dev)
+    torch.cuda.synchronize()
+    assert torch.equal(out1, out2)
+
+
+# --------------------------------------------------------------- full-size configurations
+
+@pytest.mark.parametrize("precision,tol_l,tol_g", [("f32", 1e-5, 1e-3), ("f64", 1e-12, 1e-10)])
+def test_nuc128_full_size(precision, tol_l, tol_g):
+    """The benchmark workload at full size (128 taxa, 100,000 patterns, rescaling every 4
+    levels) against the stored full-size oracle result."""
+    gold = golden("nuc128")
+    if gold is None:
+        pytest.skip("tests/golden/oracle_nuc128.json not generated")
+    wl = synth.config_workload("nuc128")
+    announce(f"nuc128 full size {precision}")
+    inst = make_instance(wl, precision, "every_k", 4)
+    lnl, g = inst.evaluate(wl.t)
+    assert rel(lnl, gold["lnl"]) < tol_l
+    assert grad_err(g, np.array(gold["grad"])) < tol_g
+    # sampled site log-likelihoods from the operation-level root call
+    inst.update_matrices(np.arange(254), wl.t[:254])
+    inst.update_post(post_ops(wl.tree.children, 128, rescale=1))
+    lnl2, site = inst.root_lnl(254, site=True)
+    idx = np.array(gold["site_idx"])
+    assert np.allclose(site[idx], gold["site_lnl"], rtol=tol_l, atol=0)
+    assert rel(lnl2, gold["lnl"]) < tol_l
+
+
+# --------------------------------------------------------------- errors
+
+def test_error_codes():
+    from paper_2606_27607_amd import HPError
+    from paper_2606_27607_amd import _lib
+    wl = synth.make_workload("gtr", 6, 50, seed=11)
+    inst = make_instance(wl, "f64", "every_node")
+    t = wl.t.copy()
+    t[2] = np.nan
+    with pytest.raises(HPError) as e:
+        inst.evaluate(t)
+    assert e.value.code == _lib.HP_ERR_VALUE
+    t[2] = -0.1
+    with pytest.raises(HPError) as e:
+        inst.update_matrices([2], [t[2]])
+    assert e.value.code == _lib.HP_ERR_VALUE
+    bad = wl.tips[0].copy()
+    bad[3] = 9
+    with pytest.raises(HPError) as e:
+        inst.set_tip_states(0, bad)
+    assert e.value.code == _lib.HP_ERR_VALUE
+    with pytest.raises(HPError) as e:
+        inst.update_post([[3, 0, 1, 1, 1, 1]])                 # dest is a tip
+    assert e.value.code == _lib.HP_ERR_INDEX
+    with pytest.raises(HPError) as e:
+        inst.update_post([[6, 0, 99, 1, 1, 1]])                # matrix out of range
+    assert e.value.code == _lib.HP_ERR_INDEX
+    with pytest.raises(HPError) as e:
+        inst.pre_gradients([[-1, 0, 0, -1, 0, 1, 1, -1, 0]], 10)  # slot used twice
+    assert e.value.code == _lib.HP_ERR_ARG
+    with pytest.raises(HPError) as e:
+        inst.set_frequencies(np.full(4, 0.3))
+    assert e.value.code == _lib.HP_ERR_VALUE
+    from paper_2606_27607_amd import Instance
+    blank = Instance(6, 50, 4, 4, precision="f64")
+    with pytest.raises(HPError) as e:
+        blank.evaluate(wl.t)
+    assert e.value.code == _lib.HP_ERR_STATE
+    # the instance still works after all the rejected calls
+    lnl, g = inst.evaluate(wl.t)
+    assert rel(lnl, oracle_eval(wl, want_grad=False)[0]) < 1e-12
+    # device-side validation of branch lengths in the stream-ordered path
+    import torch
+    td = torch.tensor(np.r_[wl.t[:9], -1.0], dtype=torch.float64, device="cuda")
+    inst.evaluate_device(td)
+    with pytest.raises(HPError) as e:
+        inst.status()
+    assert e.value.code == _lib.HP_ERR_VALUE
+    inst.status()                                               # cleared
