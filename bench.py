@@ -35,6 +35,24 @@ def algorithmic_bytes(n_tips: int, n_patterns: int, n_states: int, n_cat: int, e
     return 5.0 * (n_tips - 2) * E * elem + 2.0 * n_tips * n_patterns
 
 
+def measured_traffic(kernel_source: str, workload: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source (its sha256 must match); None otherwise."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, kernel_source)
+    if not os.path.exists(src):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.traffic.json")):
+        with open(path) as f:
+            rec = json.load(f)
+        if (rec.get("source") == kernel_source and rec.get("source_sha256") == sha
+                and rec.get("workload") == workload and rec.get("precision") == precision):
+            return rec["bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(wl, sample_patterns: int):
     """The FP64 oracle on the first `sample_patterns` patterns, one thread, scaled to evals/s
     of the full workload."""
@@ -67,7 +85,20 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=60000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=50)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (10 times), the "
+                         "reference for scaling HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 10}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the pattern "
               "partition across GPUs is a design note, not part of this build)", file=sys.stderr)
@@ -135,6 +166,8 @@ def main():
     elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.precision]
     alg = algorithmic_bytes(N, P, S, K, elem)
     achieved = alg / (trav_ms * 1e-3) / 1e9
+    traffic = measured_traffic("paper_2606_27607_amd/csrc/kernels_small.hip", args.workload,
+                               args.precision)
 
     # synchronous latency: host branch lengths in, lnL + gradients on the host out
     lat = []
@@ -154,7 +187,7 @@ def main():
                    "taxa": N, "patterns": P, "states": S, "categories": K,
                    "precision": args.precision, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "walk_small (fused post-order + root + pre-order + gradients)",
                      "kernel_ms": trav_ms, "algorithmic_bytes": alg},
         "kernels_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
