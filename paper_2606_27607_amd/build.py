@@ -36,7 +36,9 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+    # longest translation units first so the parallel build finishes sooner
+    srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp"))]
+    return sorted(srcs, key=lambda f: (not os.path.basename(f).startswith("kernels_mfma_"), f))
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:

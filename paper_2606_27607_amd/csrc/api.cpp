@@ -92,15 +92,18 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     const int S = d.n_states, K = d.n_categories;
     const bool lowp = d.precision == HP_PREC_BF16 || d.precision == HP_PREC_F16;
     int S_pad;
-    if (S <= 4) S_pad = 4;
-    else if (lowp) S_pad = S <= 32 ? 32 : 64;
-    else S_pad = (S + 3) / 4 * 4;
+    if (S <= 4) S_pad = 4;                 // vector-ALU path
+    else S_pad = S <= 32 ? 32 : 64;        // matrix-core path: MFMA tiles of 16 states
     const int P_pad = (d.n_patterns + kWave - 1) / kWave * kWave;
     const int elem = d.precision == HP_PREC_F64 ? 8 : d.precision == HP_PREC_F32 ? 4 : 2;
     const int celem = d.precision == HP_PREC_F64 ? 8 : 4;  // matrices / Q / freqs: FP64 or FP32
     const size_t np = (size_t)d.n_partials, nm = (size_t)d.n_matrices, ne = (size_t)d.n_eigen;
-    const int n_blocks = P_pad / kWave;
     Layout l{};
+    const bool mfma = S_pad > 4;
+    l.tile = mfma ? kMfmaTile : kWave;
+    l.n_blocks = P_pad / l.tile;
+    if (mfma && l.n_blocks > kMaxMfmaBlocks) l.n_blocks = kMaxMfmaBlocks;
+    const int n_blocks = l.n_blocks;
     l.post_stride = (size_t)K * P_pad * S_pad;
     l.mat_stride = (size_t)K * S_pad * S_pad;
     l.tip_stride = (size_t)K * (S + 1) * S_pad;
@@ -117,13 +120,16 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     l.post = take(np * l.post_stride * elem);
     l.post_exp = take(np * P_pad * 4);
     l.pre = take(np * l.post_stride * elem);
-    // matrices: FP64/FP32 copies always; low precision adds packed MFMA operands after them
-    size_t mats_bytes = nm * l.mat_stride * celem;
-    if (lowp) mats_bytes += nm * l.mat_stride * 2 * 2;  // P and P^T in 16-bit
-    l.mats = take(mats_bytes);
+    l.mats = take(nm * l.mat_stride * celem);
+    if (mfma) l.matsT = take(nm * l.mat_stride * celem);
+    if (lowp) {  // hi and lo 16-bit parts of P and P^T (lo only used for BF16)
+        l.mats16 = take(nm * l.mat_stride * 2 * 2);
+        l.matsT16 = take(nm * l.mat_stride * 2 * 2);
+    }
     l.tiptab = take(nm * l.tip_stride * celem);
     l.eig = take(ne * l.eig_stride * 8);
     l.Qc = take(ne * S_pad * S_pad * celem);
+    if (lowp) l.Q16 = take(ne * S_pad * S_pad * 2 * 2);
     l.freq_c = take(ne * S_pad * celem);
     l.freq_d = take(ne * S_pad * 8);
     l.cat_d = take(2 * kMaxCategories * 8);
@@ -272,7 +278,7 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
         delete I;
         return fail(nullptr, HP_ERR_WORKSPACE, "workspace smaller than hp_workspace_bytes");
     }
-    I->n_blocks = I->P_pad / hp::kWave;
+    I->n_blocks = I->L.n_blocks;
     I->ws = static_cast<uint8_t*>(dev_workspace);
     I->ws_bytes = workspace_bytes;
     I->stream = static_cast<hipStream_t>(hip_stream);
@@ -447,6 +453,25 @@ int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv
     if (rc) return rc;
     rc = upload_compute(I, I->L.Qc + (size_t)idx * Sp * Sp * (I->d.precision == HP_PREC_F64 ? 8 : 4), Q);
     if (rc) return rc;
+    if (I->L.Q16) {
+        // hi part, then (BF16) the lo part Q - hi, so that a matrix product with Q in two
+        // 16-bit MFMAs carries ~2^-17 relative error in Q instead of 2^-9
+        const size_t n = Q.size();
+        std::vector<uint16_t> hi(n), lo(n, 0);
+        for (size_t i = 0; i < n; ++i) {
+            if (I->d.precision == HP_PREC_BF16) {
+                hi[i] = hp::to_bf16_bits(Q[i]);
+                lo[i] = hp::to_bf16_bits(Q[i] - hp::bf16_bits_to_double(hi[i]));
+            } else {
+                hi[i] = hp::to_f16_bits(Q[i]);
+            }
+        }
+        const size_t ne = (size_t)I->d.n_eigen;
+        rc = upload(I, I->ws + I->L.Q16 + (size_t)idx * Sp * Sp * 2, hi.data(), n * 2);
+        if (rc) return rc;
+        rc = upload(I, I->ws + I->L.Q16 + (ne + idx) * Sp * Sp * 2, lo.data(), n * 2);
+        if (rc) return rc;
+    }
     I->eigen_set[idx] = 1;
     return HP_OK;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,8 @@ constexpr int kMaxCategories = 8;
 constexpr int kMaxStates = 64;
 constexpr int kPostOpInts = 6;     // hp_post_op
 constexpr int kPreOpInts = 9;      // hp_pre_op
+constexpr int kMfmaTile = 16;      // patterns per matrix-core tile
+constexpr int kMaxMfmaBlocks = 2048;
 
 // Device status bits (hp_status).
 constexpr int kStatusValue = 1;    // invalid branch length seen by the matrix kernel
@@ -34,11 +37,15 @@ struct Layout {
     // byte offsets into the workspace
     size_t tips, pweights, post, post_exp, pre, mats, tiptab, eig, Qc, freq_c, freq_d, cat_d,
         t_stage, idx_stage, ops_stage, tree_ops, partials, results, status, site, total;
+    // matrix-core path only: P^T in the compute type, and 16-bit P, P^T and Q operands
+    size_t matsT = 0, mats16 = 0, matsT16 = 0, Q16 = 0;
     size_t post_stride;   // elements per partial buffer (K * P_pad * S_pad)
     size_t mat_stride;    // elements per matrix slot (K * S_pad * S_pad)
     size_t tip_stride;    // elements per tip-table slot (K * (S+1) * S_pad)
     size_t eig_stride;    // doubles per eigen slot (2 S^2 + S)
     int max_out;          // output slots per reduction row (1 + max gradients)
+    int tile;             // patterns per traversal tile (64 vector path, 16 matrix-core path)
+    int n_blocks;         // workgroups of one traversal launch = columns of a reduction row
 };
 
 // Kernel classes timed by hp_profile.
@@ -70,6 +77,28 @@ struct Instance {
 
     template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
+
+// Host-side round-to-nearest-even conversions for the 16-bit copies of Q.
+inline uint16_t to_bf16_bits(double v) {
+    float f = static_cast<float>(v);
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+inline double bf16_bits_to_double(uint16_t b) {
+    uint32_t u = static_cast<uint32_t>(b) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+inline uint16_t to_f16_bits(double v) {
+    _Float16 h = static_cast<_Float16>(static_cast<float>(v));
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
 
 // Layout computation shared by hp_workspace_bytes and hp_create.
 int compute_layout(const hp_desc& d, int* S_pad, int* P_pad, int* elem, Layout* L);

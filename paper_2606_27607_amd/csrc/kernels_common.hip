@@ -6,9 +6,7 @@
 namespace hp {
 
 hipError_t launch_walk_small(const Instance& I, const WalkArgs& w);
-hipError_t launch_walk_generic(const Instance& I, const WalkArgs& w);
 hipError_t launch_walk_mfma(const Instance& I, const WalkArgs& w);
-hipError_t launch_pmat_mfma_extra(const Instance& I, const int32_t* d_idx, int count);
 
 namespace {
 
@@ -19,11 +17,14 @@ namespace {
 //   tiptab[m][k][s][x]      = P[x][s]  (s < S)     column s: the propagated one-hot tip
 //   tiptab[m][k][S][x]      = sum_y P[x][y]         the propagated all-ones (unknown) tip
 // A negative or non-finite t raises kStatusValue and writes NaN.
-template <typename T>
+// Matrix-core path extras (null when unused): matsT[m][k][y][x] = P[x][y] in T, and 16-bit
+// copies of P and P^T in H (negative rounding residues clamped to 0 before the cast).
+template <typename T, typename H>
 __global__ void __launch_bounds__(256)
 pmat_kernel(const double* __restrict__ eig, const double* __restrict__ cat_r,
             const int32_t* __restrict__ idx, const double* __restrict__ t, int K, int S, int S_pad,
-            T* __restrict__ mats, T* __restrict__ tiptab, int32_t* __restrict__ status) {
+            T* __restrict__ mats, T* __restrict__ tiptab, T* __restrict__ matsT, H* __restrict__ m16,
+            H* __restrict__ mT16, size_t lo_off, int32_t* __restrict__ status) {
     __shared__ double W[kMaxStates * kMaxStates];  // W[j][y] = exp(lam_j r t) Vinv[j][y]
     __shared__ double rs[kMaxStates];              // rs[j] = exp(lam_j r t) sum_y Vinv[j][y]
     const int i = blockIdx.x, k = blockIdx.y;
@@ -56,6 +57,20 @@ pmat_kernel(const double* __restrict__ eig, const double* __restrict__ cat_r,
         if (bad) v = NAN;
         Pm[e] = T(v);
         if (y < S) Tt[y * S_pad + x] = T(v);
+        const size_t base = (size_t)(m * K + k) * S_pad * S_pad;
+        if (matsT) matsT[base + (size_t)y * S_pad + x] = T(v);
+        if (m16) {
+            // hi part at base, lo part (value - hi, BF16 only) one full matrix array later
+            const float c = v > 0.0 ? float(v) : (bad ? float(v) : 0.0f);
+            const H hi = H(c);
+            const H lo = lo_off ? H(c - float(hi)) : H(0.0f);
+            m16[base + e] = hi;
+            mT16[base + (size_t)y * S_pad + x] = hi;
+            if (lo_off) {
+                m16[lo_off + base + e] = lo;
+                mT16[lo_off + base + (size_t)y * S_pad + x] = lo;
+            }
+        }
     }
     for (int x = threadIdx.x; x < S_pad; x += blockDim.x) {
         double v = 0.0;
@@ -106,29 +121,39 @@ hipError_t launch_pmat(const Instance& I, int eigen_idx, const int32_t* d_idx, c
     const double* eig = I.at<double>(L.eig) + (size_t)eigen_idx * L.eig_stride;
     dim3 grid(count, I.d.n_categories), block(256);
     const int S = I.d.n_states;
+    const int32_t* di = d_idx;
+    int32_t* st = I.at<int32_t>(L.status);
+    const double* cr = I.at<double>(L.cat_d);
+    const int K = I.d.n_categories, Sp = I.S_pad;
+    const size_t lo_all = (size_t)I.d.n_matrices * L.mat_stride;  // elements per 16-bit array
     switch (I.d.precision) {
         case HP_PREC_F64:
-            hipLaunchKernelGGL(pmat_kernel<double>, grid, block, 0, I.stream, eig, I.at<double>(L.cat_d),
-                               d_idx, d_t, I.d.n_categories, S, I.S_pad, I.at<double>(L.mats),
-                               I.at<double>(L.tiptab), I.at<int32_t>(L.status));
+            hipLaunchKernelGGL((pmat_kernel<double, _Float16>), grid, block, 0, I.stream, eig, cr, di, d_t,
+                               K, S, Sp, I.at<double>(L.mats), I.at<double>(L.tiptab),
+                               L.matsT ? I.at<double>(L.matsT) : nullptr, nullptr, nullptr, 0, st);
+            break;
+        case HP_PREC_F32:
+            hipLaunchKernelGGL((pmat_kernel<float, _Float16>), grid, block, 0, I.stream, eig, cr, di, d_t,
+                               K, S, Sp, I.at<float>(L.mats), I.at<float>(L.tiptab),
+                               L.matsT ? I.at<float>(L.matsT) : nullptr, nullptr, nullptr, 0, st);
+            break;
+        case HP_PREC_BF16:
+            hipLaunchKernelGGL((pmat_kernel<float, __bf16>), grid, block, 0, I.stream, eig, cr, di, d_t,
+                               K, S, Sp, I.at<float>(L.mats), I.at<float>(L.tiptab), I.at<float>(L.matsT),
+                               I.at<__bf16>(L.mats16), I.at<__bf16>(L.matsT16), lo_all, st);
             break;
         default:
-            hipLaunchKernelGGL(pmat_kernel<float>, grid, block, 0, I.stream, eig, I.at<double>(L.cat_d),
-                               d_idx, d_t, I.d.n_categories, S, I.S_pad, I.at<float>(L.mats),
-                               I.at<float>(L.tiptab), I.at<int32_t>(L.status));
+            hipLaunchKernelGGL((pmat_kernel<float, _Float16>), grid, block, 0, I.stream, eig, cr, di, d_t,
+                               K, S, Sp, I.at<float>(L.mats), I.at<float>(L.tiptab), I.at<float>(L.matsT),
+                               I.at<_Float16>(L.mats16), I.at<_Float16>(L.matsT16), 0, st);
             break;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (I.d.precision == HP_PREC_BF16 || I.d.precision == HP_PREC_F16)
-        return launch_pmat_mfma_extra(I, d_idx, count);
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 hipError_t launch_walk(const Instance& I, const WalkArgs& w) {
-    if (I.d.precision == HP_PREC_BF16 || I.d.precision == HP_PREC_F16) return launch_walk_mfma(I, w);
     if (I.S_pad == 4) return launch_walk_small(I, w);
-    return launch_walk_generic(I, w);
+    return launch_walk_mfma(I, w);
 }
 
 hipError_t launch_reduce(const Instance& I, int n_out, double* d_out) {

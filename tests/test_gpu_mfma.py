@@ -1,0 +1,114 @@
+"""GPU parity of the matrix-core path (4 < S <= 64: amino-acid and codon models) against the
+FP64 oracle, in FP64, FP32, BF16 and FP16.
+
+Tolerances: FP64 1e-12 relative on lnL and 1e-9 of max|g| (61-term contractions at every
+node and pattern sums of both signs: observed ~2e-11); FP32 1e-5 relative on lnL and
+1e-3 of max|g|; BF16/FP16 1e-4 relative on lnL (the mixed-precision bound) and a stated
+gradient error, bounded here at 5e-2 of max|g| for BF16 and 1e-2 for FP16 (16-bit partials
+carry 2^-9 / 2^-12 relative rounding per stored value).
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import announce, golden, grad_err, make_instance, oracle_eval, post_ops, pre_ops, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": (1e-12, 1e-9), "f32": (1e-5, 1e-3), "bf16": (1e-4, 5e-2), "f16": (1e-4, 1e-2)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("kind,n,npat,seed", [("gy94", 12, 300, 1), ("aa", 17, 200, 2),
+                                              ("gy94", 3, 37, 3), ("aa", 40, 130, 4)])
+def test_evaluate_matches_oracle(precision, kind, n, npat, seed):
+    wl = synth.make_workload(kind, n, npat, seed=seed, unknown_frac=0.05)
+    inst = make_instance(wl, precision, "every_node")
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    tl, tg = TOL[precision]
+    assert rel(lnl, lnl_o) < tl, (lnl, lnl_o)
+    assert grad_err(g, g_o) < tg
+    assert inst.evaluate(wl.t, want_grad=False) == lnl
+
+
+@pytest.mark.parametrize("S", [5, 13, 33, 64])
+def test_odd_state_counts_fp64(S):
+    rng = np.random.default_rng(S)
+    pi = rng.dirichlet(np.ones(S) * 5)
+    R = np.zeros((S, S))
+    R[np.triu_indices(S, 1)] = rng.gamma(1.0, 1.0, S * (S - 1) // 2)
+    Q = synth.models.reversible(R + R.T, pi)
+    wl = synth.make_workload("gtr", 9, 90, seed=S)
+    V, Vinv, lam = synth.eigensystem(Q, pi)
+    wl.Q, wl.pi, wl.V, wl.Vinv, wl.lam = Q, pi, V, Vinv, lam
+    wl.tips = rng.integers(0, S + 1, size=(9, 90)).astype(np.uint8)
+    inst = make_instance(wl, "f64", "every_node")
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    assert rel(lnl, lnl_o) < 1e-12 and grad_err(g, g_o) < 1e-9
+
+
+@pytest.mark.parametrize("K", [1, 6])
+def test_category_counts_mfma(K):
+    wl = synth.make_workload("gy94", 8, 100, seed=K, n_categories=K)
+    inst = make_instance(wl, "f32", "every_node")
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    assert rel(lnl, lnl_o) < 1e-5 and grad_err(g, g_o) < 1e-3
+
+
+@pytest.mark.parametrize("precision", ["f64", "bf16"])
+def test_op_level_api_mfma(precision):
+    wl = synth.make_workload("gy94", 10, 150, seed=9, unknown_frac=0.05)
+    inst = make_instance(wl, precision, "every_node", tree=False)
+    N = wl.n_tips
+    nb = 2 * N - 2
+    inst.update_matrices(np.arange(nb), wl.t[:nb])
+    inst.update_post(post_ops(wl.tree.children, N, rescale=1))
+    lnl, site = inst.root_lnl(2 * N - 2, site=True)
+    lnl_o, site_o, g_o = oracle_eval(wl)
+    tl, tg = TOL[precision]
+    assert rel(lnl, lnl_o) < tl
+    # per-site log-likelihoods: absolute error in nats (BF16 partials round to 2^-9 at
+    # every node, so a site carries ~sqrt(nodes) * 2^-9 of noise that averages out in lnL)
+    site_tol = {"f64": 1e-9, "bf16": 0.05}[precision]
+    err = np.abs(site - site_o).max()
+    print(f"{precision}: max |site lnL error| {err:.3e} nats")
+    assert err < site_tol
+    g = inst.pre_gradients(pre_ops(wl.tree.children, N), nb)
+    assert grad_err(g, g_o) < tg
+
+
+def test_many_tiles_per_workgroup_and_determinism():
+    """More 16-pattern tiles than workgroups (each workgroup loops over tiles)."""
+    wl = synth.make_workload("aa", 6, 40_000, seed=10)
+    inst = make_instance(wl, "f32", "every_node")
+    a = inst.evaluate(wl.t)
+    b = inst.evaluate(wl.t)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+    lnl_o, _, g_o = oracle_eval(wl)
+    assert rel(a[0], lnl_o) < 1e-5 and grad_err(a[1], g_o) < 1e-3
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16", "f16"])
+def test_codon64_full_size(precision):
+    gold = golden("codon64")
+    if gold is None:
+        pytest.skip("tests/golden/oracle_codon64.json not generated")
+    wl = synth.config_workload("codon64")
+    announce(f"codon64 full size {precision}")
+    inst = make_instance(wl, precision, "every_node")
+    lnl, g = inst.evaluate(wl.t)
+    tl, tg = TOL[precision]
+    print(f"codon64 {precision}: lnL rel err {rel(lnl, gold['lnl']):.3e}, "
+          f"grad err {grad_err(g, np.array(gold['grad'])):.3e}")
+    assert rel(lnl, gold["lnl"]) < tl
+    assert grad_err(g, np.array(gold["grad"])) < tg
