@@ -8,8 +8,9 @@ branch lengths (multiplicative N(0, 0.05) perturbations, as an MCMC proposal wou
 
 Prints one JSON line (rank 0, N = 1) with the throughput, the roofline of the dominant
 kernel (the traversal kernel, timed live with HIP events on the library's stream), the
-error against the FP64 oracle, synchronous-call latency percentiles and the oracle timed
-on a bounded sample of the same workload on the host cores.
+error against the FP64 oracle, synchronous-call latency percentiles, the oracle timed on a
+bounded sample of the same workload on the host cores, and the same measurements for the
+FP64 form and for the 64-taxon codon workload in FP32 / BF16 / FP16 / FP64 ("variants").
 """
 from __future__ import annotations
 
@@ -24,6 +25,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lnL+gradient evals/s vs plain FP32 at stated error; %roofline; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+# dense matrix-core peaks of MI355X per operand type, TFLOP/s
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f16": 2500.0, "f32": 157.3, "f64": 78.6}
+ELEM = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+KERNEL_SOURCES = {True: "paper_2606_27607_amd/csrc/kernels_small.hip",
+                  False: "paper_2606_27607_amd/csrc/walk_mfma.inc"}
 
 
 def algorithmic_bytes(n_tips: int, n_patterns: int, n_states: int, n_cat: int, elem: int) -> float:
@@ -33,6 +39,13 @@ def algorithmic_bytes(n_tips: int, n_patterns: int, n_states: int, n_cat: int, e
     the tip states read once in each pass (2 N P bytes).  E = P K S (algorithmic S)."""
     E = n_patterns * n_cat * n_states
     return 5.0 * (n_tips - 2) * E * elem + 2.0 * n_tips * n_patterns
+
+
+def algorithmic_flops(n_tips: int, n_patterns: int, n_states: int, n_cat: int) -> float:
+    """Flops of one full evaluation: one matrix-vector product (2 S^2) per pattern and
+    category for every internal child edge in the post-order pass, and three (recomputed
+    P post, P^T (pre o u), Q u) in the pre-order pass; tip edges are lookups."""
+    return 4.0 * (n_tips - 2) * n_patterns * n_cat * 2.0 * n_states ** 2
 
 
 def measured_traffic(kernel_source: str, workload: str, precision: str):
@@ -75,6 +88,134 @@ def cpu_baseline(wl, sample_patterns: int):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def measure(wl, precision: str, steps: int, warmup: int, latency_samples: int) -> dict:
+    import numpy as np
+    import torch
+
+    from paper_2606_27607_amd import Instance
+
+    N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
+    nb = 2 * N - 2
+    small = S <= 4
+    if small:
+        period = max(1, wl.meta.get("scale_every", 4))
+        inst = Instance(N, P, S, K, precision=precision, scaling="every_k", scale_period=period)
+        scaling = f"rescaling every {period} levels"
+    else:
+        inst = Instance(N, P, S, K, precision=precision, scaling="every_node")
+        scaling = "rescaling every node"
+    inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
+              children=wl.tree.children)
+    dev = inst.device
+    rng = np.random.default_rng(1)
+    n_sets = steps + warmup
+    t_all = wl.t[:nb][None, :] * np.exp(0.05 * rng.standard_normal((n_sets, nb)))
+    t_dev = torch.tensor(t_all, dtype=torch.float64, device=dev)
+    out = torch.empty((n_sets, 1 + nb), dtype=torch.float64, device=dev)
+
+    # accuracy at the workload's own branch lengths, against the full-size FP64 oracle
+    lnl, g = inst.evaluate(wl.t)
+    err = {}
+    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{wl.name}.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+        gg = np.array(gold["grad"])
+        err = {"lnl_rel": abs(lnl - gold["lnl"]) / abs(gold["lnl"]),
+               "lnl_abs": abs(lnl - gold["lnl"]),
+               "grad_maxabs_over_maxabs": float(np.max(np.abs(g - gg)) / np.max(np.abs(gg))),
+               "grad_l2_rel": float(np.linalg.norm(g - gg) / np.linalg.norm(gg)),
+               "reference": "FP64 oracle, full workload"}
+
+    for i in range(warmup):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    torch.cuda.synchronize()
+    inst.status()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, n_sets):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    inst.status()
+    ms_per_step = 1000.0 * elapsed / steps
+
+    # the same steps again with every kernel bracketed by HIP events on the library's stream
+    inst.profile(True)
+    inst.profile_read()
+    for i in range(warmup, n_sets):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    prof = inst.profile_read()
+    inst.profile(False)
+    trav_ms = prof["traversal"][0] / max(1, prof["traversal"][1])
+    alg = algorithmic_bytes(N, P, S, K, ELEM[precision])
+    gbs = alg / (trav_ms * 1e-3) / 1e9
+    traffic = measured_traffic(KERNEL_SOURCES[small], wl.name, precision)
+    if small:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "walk_small (fused post-order + root + pre-order + gradients)",
+                "kernel_ms": trav_ms, "algorithmic_bytes": alg}
+    else:
+        fl = algorithmic_flops(N, P, S, K)
+        tf = fl / (trav_ms * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFLOPS[precision]
+        roof = {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                "frac": tf / peak, "traffic": traffic,
+                "kernel": f"walk_mfma<{precision}> (fused post-order + root + pre-order + gradients)",
+                "kernel_ms": trav_ms, "algorithmic_flops": fl, "algorithmic_bytes": alg,
+                "hbm_GBs_algorithmic": gbs, "hbm_frac_algorithmic": gbs / HBM_PEAK_GBS}
+
+    lat = []
+    for i in range(latency_samples):
+        s = time.perf_counter()
+        inst.evaluate(t_all[i % n_sets])
+        lat.append(1000.0 * (time.perf_counter() - s))
+    inst.close()
+    return {
+        "value": 1000.0 / ms_per_step, "unit": "evals/s", "ms_per_step": ms_per_step,
+        "dtype": precision,
+        "config": {"workload": f"{wl.name}: {N}-taxon Yule tree, {wl.meta['kind'].upper()}+G{K} "
+                               f"(alpha 0.5), {P} simulated patterns, S={S}, {scaling}, "
+                               f"lnL + all {nb} branch gradients per eval",
+                   "taxa": N, "patterns": P, "states": S, "categories": K, "precision": precision},
+        "roofline": roof,
+        "kernels_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+        "error_vs_oracle": err,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mode": "synchronous hp_evaluate, host in/out"} if lat else None,
+    }
+
+
+def measure_autograd(wl, precision: str, steps: int) -> dict:
+    """Forward + backward of BranchLengthLnL per mode (store / recompute / fused), ms per step."""
+    import torch
+
+    from paper_2606_27607_amd import Instance
+    from paper_2606_27607_amd.autograd import BranchLengthLnL
+
+    N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
+    scaling = ("every_k", 4) if S <= 4 else ("every_node", 1)
+    inst = Instance(N, P, S, K, precision=precision, scaling=scaling[0], scale_period=scaling[1])
+    inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
+              children=wl.tree.children)
+    t = torch.tensor(wl.t[: 2 * N - 2], dtype=torch.float64, device=inst.device, requires_grad=True)
+    res = {}
+    for mode in ("store", "recompute", "fused"):
+        for i in range(3 + steps):
+            if i == 3:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            out = BranchLengthLnL.apply(t, inst, mode)
+            (g,) = torch.autograd.grad(out, t)
+        torch.cuda.synchronize()
+        res[mode] = {"ms_per_forward_backward": 1000.0 * (time.perf_counter() - t0) / steps}
+    inst.close()
+    return {"workload": f"{wl.name}: {N} taxa, {P} patterns, S={S}", "precision": precision,
+            "modes": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +225,7 @@ def main():
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--cpu-sample", type=int, default=60000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=50)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
@@ -104,100 +246,44 @@ def main():
               "partition across GPUs is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
     import synth
-    from paper_2606_27607_amd import Instance
 
-    print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
+    print(f"[bench] workload {args.workload} {args.precision}", file=sys.stderr, flush=True)
     wl = synth.config_workload(args.workload)
-    N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
-    nb = 2 * N - 2
-    period = max(1, wl.meta.get("scale_every", 4))
-    inst = Instance(N, P, S, K, precision=args.precision, scaling="every_k", scale_period=period)
-    inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
-              children=wl.tree.children)
-    dev = inst.device
-    rng = np.random.default_rng(1)
-    n_sets = args.steps + args.warmup
-    t_all = wl.t[:nb][None, :] * np.exp(0.05 * rng.standard_normal((n_sets, nb)))
-    t_dev = torch.tensor(t_all, dtype=torch.float64, device=dev)
-    out = torch.empty((n_sets, 1 + nb), dtype=torch.float64, device=dev)
-
-    # accuracy at the workload's own branch lengths
-    lnl, g = inst.evaluate(wl.t)
-    err = {}
-    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}.json")
-    if os.path.exists(gold_path):
-        with open(gold_path) as f:
-            gold = json.load(f)
-        gg = np.array(gold["grad"])
-        err = {"lnl_rel": abs(lnl - gold["lnl"]) / abs(gold["lnl"]),
-               "lnl_abs": abs(lnl - gold["lnl"]),
-               "grad_maxabs_over_maxabs": float(np.max(np.abs(g - gg)) / np.max(np.abs(gg))),
-               "grad_l2_rel": float(np.linalg.norm(g - gg) / np.linalg.norm(gg)),
-               "reference": "FP64 oracle, full workload"}
-
-    print("[bench] warmup", file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        inst.evaluate_device(t_dev[i], out=out[i])
-    torch.cuda.synchronize()
-    inst.status()
-
-    print("[bench] timed region", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, n_sets):
-        inst.evaluate_device(t_dev[i], out=out[i])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    inst.status()
-    ms_per_step = 1000.0 * elapsed / args.steps
-
-    # the same steps again with every kernel bracketed by HIP events on the library's stream
-    inst.profile(True)
-    inst.profile_read()
-    for i in range(args.warmup, n_sets):
-        inst.evaluate_device(t_dev[i], out=out[i])
-    prof = inst.profile_read()
-    inst.profile(False)
-    trav_ms = prof["traversal"][0] / max(1, prof["traversal"][1])
-    elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.precision]
-    alg = algorithmic_bytes(N, P, S, K, elem)
-    achieved = alg / (trav_ms * 1e-3) / 1e9
-    traffic = measured_traffic("paper_2606_27607_amd/csrc/kernels_small.hip", args.workload,
-                               args.precision)
-
-    # synchronous latency: host branch lengths in, lnL + gradients on the host out
-    lat = []
-    for i in range(args.latency_samples):
-        s = time.perf_counter()
-        inst.evaluate(t_all[i % n_sets])
-        lat.append(1000.0 * (time.perf_counter() - s))
-
-    line = {
-        "metric": METRIC, "value": 1000.0 / ms_per_step, "unit": "evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {N}-taxon Yule tree, {wl.meta['kind'].upper()}+G{K} "
-                               f"(alpha 0.5), {P} simulated patterns, S={S}, rescaling every "
-                               f"{period} levels, lnL + all {nb} branch gradients per eval",
-                   "taxa": N, "patterns": P, "states": S, "categories": K,
-                   "precision": args.precision, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "walk_small (fused post-order + root + pre-order + gradients)",
-                     "kernel_ms": trav_ms, "algorithmic_bytes": alg},
-        "kernels_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
-        "error_vs_oracle": err,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mode": "synchronous hp_evaluate, host in/out"},
-    }
+    head = measure(wl, args.precision, args.steps, args.warmup, args.latency_samples)
+    line = {"metric": METRIC, "value": head["value"], "unit": "evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": args.precision, "data": "synthetic",
+            "config": dict(head["config"], parallelism="single GPU"),
+            "roofline": head["roofline"], "kernels_ms_per_step": head["kernels_ms_per_step"],
+            "error_vs_oracle": head["error_vs_oracle"], "latency_ms": head["latency_ms"]}
+    if not args.no_variants:
+        variants = []
+        plan = [("nuc128", "f64")] if args.workload == "nuc128" else []
+        plan += [("codon64", p) for p in ("f32", "bf16", "f16", "f64")]
+        wls = {args.workload: wl}
+        for name, prec in plan:
+            if (name, prec) == (args.workload, args.precision):
+                continue
+            print(f"[bench] variant {name} {prec}", file=sys.stderr, flush=True)
+            if name not in wls:
+                wls[name] = synth.config_workload(name)
+            variants.append(measure(wls[name], prec, max(10, args.steps // 2), 3, 10))
+        line["variants"] = variants
+        by = {(v["config"]["taxa"], v["dtype"]): v for v in variants}
+        c32 = by.get((64, "f32"))
+        if c32:
+            line["codon_mixed_vs_fp32"] = {
+                p: {"speedup_vs_f32": by[(64, p)]["value"] / c32["value"],
+                    "lnl_rel_err": by[(64, p)]["error_vs_oracle"].get("lnl_rel")}
+                for p in ("bf16", "f16") if (64, p) in by}
+        print("[bench] autograd modes", file=sys.stderr, flush=True)
+        line["autograd"] = [measure_autograd(synth.config_workload("nuc256"), "f32", 20),
+                            measure_autograd(synth.config_workload("codon32"), "bf16", 20)]
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, P))
+        line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, wl.n_patterns))
     print(json.dumps(line), flush=True)
 
 

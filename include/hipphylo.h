@@ -218,6 +218,14 @@ int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_l
  * output NaN and raises the status word read by hp_status (HP_ERR_VALUE). */
 int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, double* d_out);
 
+/* Pre-order partials and all 2N-2 branch gradients of the tree of hp_set_tree from the
+ * post-order partials and transition matrices left by the preceding
+ * hp_evaluate_device(want_grad = 0) on this instance (the "store" form of a backward pass:
+ * nothing from the forward pass is recomputed).  d_grad: device pointer, 2N-2 FP64 values
+ * indexed by node.  Stream-ordered; the caller must not have changed the partials or the
+ * matrices in between (the library cannot detect it). */
+int hp_gradients_device(hp_instance* inst, double* d_grad);
+
 /* Synchronise the stream and return (then clear) the device-side status of work enqueued
  * since the last call: HP_OK, HP_ERR_VALUE or HP_ERR_NUMERIC. */
 int hp_status(hp_instance* inst);

@@ -832,6 +832,24 @@ int hp_profile_read(hp_instance* inst, double* out_ms, int64_t* out_count) {
     return HP_OK;
 }
 
+int hp_gradients_device(hp_instance* inst, double* d_grad) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!d_grad) return fail(I, HP_ERR_ARG, "NULL argument");
+    int rc = check_eval_state(I);
+    if (rc) return rc;
+    const int N = I->d.n_tips;
+    DeviceGuard g(I->d.device);
+    hp::WalkArgs a;
+    a.mode = hp::kPre | hp::kGrad;
+    a.pre_ops = I->at<int32_t>(I->L.tree_ops) + (size_t)(N - 1) * hp::kPostOpInts;
+    a.n_pre = I->tree_n_pre;
+    a.n_grad = 2 * N - 2;
+    HP_HIP(I, HP_WALK(*I, a));
+    HP_HIP(I, HP_REDUCE(*I, a.n_grad, d_grad, 1));
+    return HP_OK;
+}
+
 int hp_status(hp_instance* inst) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);

@@ -56,6 +56,7 @@ class Instance:
         self.workspace_bytes = nbytes.value
         self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         self._inst = ctypes.c_void_p()
+        self.generation = 0  # bumped by every call that may change partials or matrices
         stream = torch.cuda.current_stream(self.device).cuda_stream
         check(self._lib, self._lib.hp_create(ctypes.byref(self.desc),
                                              ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
@@ -63,7 +64,13 @@ class Instance:
         self._stream = stream
 
     # ------------------------------------------------------------------ plumbing
+    # calls that leave the partial buffers and matrices as they were
+    _PURE = frozenset({"hp_status", "hp_query", "hp_profile", "hp_profile_read", "hp_set_stream",
+                       "hp_gradients_device", "hp_last_error"})
+
     def _call(self, name, *args):
+        if name not in self._PURE:
+            self.generation += 1
         return check(self._lib, getattr(self._lib, name)(self._inst, *args), self._inst)
 
     def _bind_stream(self):
@@ -196,6 +203,17 @@ class Instance:
             out = torch.empty(1 + nb if want_grad else 1, dtype=torch.float64, device=self.device)
         self._call("hp_evaluate_device", ctypes.c_void_p(t.data_ptr()), int(bool(want_grad)),
                    ctypes.c_void_p(out.data_ptr()))
+        return out
+
+    def gradients_device(self, out=None):
+        """Stream-ordered pre-order pass and all branch gradients from the post-order partials
+        of the preceding evaluate_device(..., want_grad=False); returns a CUDA float64 tensor."""
+        self._bind_stream()
+        torch = self.torch
+        nb = 2 * self.n_tips - 2
+        if out is None:
+            out = torch.empty(nb, dtype=torch.float64, device=self.device)
+        self._call("hp_gradients_device", ctypes.c_void_p(out.data_ptr()))
         return out
 
     def status(self):
