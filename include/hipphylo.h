@@ -226,6 +226,20 @@ int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, doub
  * matrices in between (the library cannot detect it). */
 int hp_gradients_device(hp_instance* inst, double* d_grad);
 
+/* ---------------------------------------------------------------- batched evaluation
+ * Whole-tree evaluations of up to HP_MAX_BATCH instances in one launch per kernel (matrix
+ * assembly, traversal, reduction), for serving many clients.  The instances must share
+ * device, precision, state padding and category count, must each have had hp_set_tree and
+ * model slot 0 set, and may each appear only once; their trees, pattern counts and models
+ * may differ.  d_t[i] (2N_i-2 FP64) and d_out[i] (1 + 2N_i-2 FP64 with gradients, else 1)
+ * are device pointers.  Work is enqueued on hip_stream (not on the instances' streams) and
+ * nothing is synchronised; each instance's device status is checked with hp_status.
+ * Results are bitwise identical to hp_evaluate_device of each instance alone.  Errors are
+ * read with hp_last_error(NULL). */
+#define HP_MAX_BATCH 32
+int hp_batch_evaluate_device(hp_instance* const* insts, const double* const* d_t,
+                             double* const* d_out, int n, int want_grad, void* hip_stream);
+
 /* Synchronise the stream and return (then clear) the device-side status of work enqueued
  * since the last call: HP_OK, HP_ERR_VALUE or HP_ERR_NUMERIC. */
 int hp_status(hp_instance* inst);

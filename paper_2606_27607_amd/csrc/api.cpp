@@ -141,6 +141,7 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     l.results = take((size_t)l.max_out * 8);
     l.status = take(64);
     l.site = take((size_t)P_pad * 8);
+    l.desc = take(3 * kDescBytes);
     l.total = off;
     *S_pad_out = S_pad;
     *P_pad_out = P_pad;
@@ -730,6 +731,16 @@ int hp_set_tree(hp_instance* inst, const int32_t* children) {
     if (rc) return rc;
     rc = upload(I, dst + (size_t)(N - 1) * hp::kPostOpInts, pre.data(), pre.size() * 4);
     if (rc) return rc;
+    // whole-tree kernel descriptors for batched evaluation: traversal with gradients,
+    // traversal without, matrix assembly (branch c uses matrix slot c)
+    std::vector<unsigned char> desc(3 * hp::kDescBytes, 0);
+    if (hp::build_tree_desc(*I, 1, desc.data()) > hp::kDescBytes ||
+        hp::build_tree_desc(*I, 0, desc.data() + hp::kDescBytes) > hp::kDescBytes)
+        return fail(I, HP_ERR_DEVICE, "kernel descriptor larger than its slot");
+    const hp::PmatDev pd = hp::build_pmat_desc(*I, 0, nullptr);
+    std::memcpy(desc.data() + 2 * hp::kDescBytes, &pd, sizeof(pd));
+    rc = upload(I, I->ws + I->L.desc, desc.data(), desc.size());
+    if (rc) return rc;
     I->tree_set = true;
     I->tree_n_post = N - 1;
     I->tree_n_pre = N - 1;
@@ -796,6 +807,51 @@ int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, doub
     if (rc) return rc;
     DeviceGuard g(I->d.device);
     return enqueue_evaluate(I, d_t, want_grad, d_out);
+}
+
+int hp_batch_evaluate_device(hp_instance* const* insts, const double* const* d_t, double* const* d_out,
+                             int n, int want_grad, void* hip_stream) {
+    if (n < 0 || n > HP_MAX_BATCH) return fail(nullptr, HP_ERR_ARG, "batch size must be in [0, HP_MAX_BATCH]");
+    if (n == 0) return HP_OK;
+    if (!insts || !d_t || !d_out) return fail(nullptr, HP_ERR_ARG, "NULL argument");
+    Instance* first = reinterpret_cast<Instance*>(insts[0]);
+    if (!first) return fail(nullptr, HP_ERR_ARG, "NULL instance");
+    hp::BatchArgs b{};
+    b.n = n;
+    int32_t wo = 0, po = 0, ro = 0;
+    for (int i = 0; i < n; ++i) {
+        Instance* I = reinterpret_cast<Instance*>(insts[i]);
+        if (!I || !d_t[i] || !d_out[i]) return fail(nullptr, HP_ERR_ARG, "NULL instance or pointer in batch");
+        for (int j = 0; j < i; ++j)
+            if (insts[j] == insts[i]) return fail(nullptr, HP_ERR_ARG, "an instance appears twice in one batch");
+        if (I->d.device != first->d.device || I->d.precision != first->d.precision ||
+            I->S_pad != first->S_pad || I->d.n_categories != first->d.n_categories)
+            return fail(nullptr, HP_ERR_UNSUPPORTED,
+                        "batched instances must share device, precision, state padding and categories");
+        if (!I->tree_set || !I->eigen_set[0] || !I->freq_set[0])
+            return fail(nullptr, HP_ERR_STATE, "a batched instance lacks its tree or model");
+        const int N = I->d.n_tips;
+        b.walk[i] = I->ws + I->L.desc + (want_grad ? 0 : hp::kDescBytes);
+        b.pmat[i] = I->ws + I->L.desc + 2 * hp::kDescBytes;
+        b.t[i] = d_t[i];
+        b.out[i] = d_out[i];
+        b.walk_off[i] = wo;
+        b.pmat_off[i] = po;
+        b.red_off[i] = ro;
+        wo += I->n_blocks;
+        po += 2 * N - 2;
+        ro += want_grad ? 2 * N - 1 : 1;
+    }
+    b.walk_off[n] = wo;
+    b.pmat_off[n] = po;
+    b.red_off[n] = ro;
+    DeviceGuard g(first->d.device);
+    hipStream_t saved = first->stream;
+    first->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hp::launch_batch(*first, b, want_grad);
+    first->stream = saved;
+    if (e != hipSuccess) return hip_fail(nullptr, e, "batched launch");
+    return HP_OK;
 }
 
 int hp_profile(hp_instance* inst, int enable) {

@@ -39,6 +39,7 @@ struct Layout {
         t_stage, idx_stage, ops_stage, tree_ops, partials, results, status, site, total;
     // matrix-core path only: P^T in the compute type, and 16-bit P, P^T and Q operands
     size_t matsT = 0, mats16 = 0, matsT16 = 0, Q16 = 0;
+    size_t desc = 0;      // whole-tree descriptors: traversal with and without gradients, matrices
     size_t post_stride;   // elements per partial buffer (K * P_pad * S_pad)
     size_t mat_stride;    // elements per matrix slot (K * S_pad * S_pad)
     size_t tip_stride;    // elements per tip-table slot (K * (S+1) * S_pad)
@@ -47,6 +48,66 @@ struct Layout {
     int tile;             // patterns per traversal tile (64 vector path, 16 matrix-core path)
     int n_blocks;         // workgroups of one traversal launch = columns of a reduction row
 };
+
+// ------------------------------------------------------------------ batched launches
+// Several instances of one class (device, precision, state padding, category count) are
+// evaluated by one launch per kernel: each instance keeps its whole-tree kernel descriptors
+// in its own workspace (written by hp_set_tree), and a batch passes only pointers and
+// block offsets as kernel arguments.
+constexpr int kMaxBatch = HP_MAX_BATCH;
+constexpr size_t kDescBytes = 512;   // one whole-tree kernel descriptor slot in the workspace
+
+// Common prefix of every traversal descriptor, read by the batched reduction.
+struct DescHead {
+    double* partials;   // [n_out][n_blocks]
+    int n_blocks;
+    int n_out;
+};
+
+struct BatchArgs {
+    const void* walk[kMaxBatch];   // per-instance traversal descriptor (device)
+    const void* pmat[kMaxBatch];   // per-instance matrix descriptor (device)
+    const double* t[kMaxBatch];    // per-request branch lengths (device, 2N-2)
+    double* out[kMaxBatch];        // per-request results (device, 1 + 2N-2 or 1)
+    int32_t walk_off[kMaxBatch + 1];
+    int32_t pmat_off[kMaxBatch + 1];
+    int32_t red_off[kMaxBatch + 1];
+    int32_t n;
+};
+
+// Matrix-assembly descriptor (the storage types are fixed by the instance's precision).
+struct PmatDev {
+    const double* eig;
+    const double* cat_r;
+    const int32_t* idx;   // null: identity
+    void* mats;
+    void* tiptab;
+    void* matsT;
+    void* m16;
+    void* mT16;
+    size_t lo_off;
+    int32_t* status;
+    int K, S, S_pad;
+};
+
+// Copy a kernel descriptor from device memory that no kernel writes, word by word through
+// the constant address space (uniform addresses: scalar loads).
+template <typename D>
+__device__ __forceinline__ D load_desc(const void* p) {
+    static_assert(sizeof(D) % 4 == 0, "descriptor size must be a multiple of 4");
+    D d;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&d);
+    const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)p;
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(D) / 4; ++i) dst[i] = src[i];
+    return d;
+}
+
+__device__ __forceinline__ int batch_find(const int32_t* off, int n, int block) {
+    int i = 0;
+    while (i + 1 < n && block >= off[i + 1]) ++i;
+    return i;
+}
 
 // Kernel classes timed by hp_profile.
 enum KernelClass : int { kPmat = 0, kTraversal = 1, kReduce = 2, kNumClasses = 3 };
@@ -120,6 +181,10 @@ struct WalkArgs {
     double* site = nullptr;
 };
 hipError_t launch_walk(const Instance& I, const WalkArgs& a);
+// Size in bytes of the traversal descriptor for whole-tree evaluation, written to host_buf.
+size_t build_tree_desc(const Instance& I, int want_grad, void* host_buf);
+PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx);
+hipError_t launch_batch(const Instance& first, const BatchArgs& b, int want_grad);
 // out[i] = sum over workgroups of reduction slot first + i, for i < n_out.
 hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first = 0);
 hipError_t launch_fill_i32(const Instance& I, int32_t* p, int32_t v, size_t n);

@@ -5,7 +5,6 @@
 
 namespace hp {
 
-hipError_t launch_walk_small(const Instance& I, const WalkArgs& w);
 hipError_t launch_walk_mfma(const Instance& I, const WalkArgs& w);
 
 namespace {
@@ -18,24 +17,20 @@ namespace {
 //   tiptab[m][k][S][x]      = sum_y P[x][y]         the propagated all-ones (unknown) tip
 // A negative or non-finite t raises kStatusValue and writes NaN.
 // Matrix-core path extras (null when unused): matsT[m][k][y][x] = P[x][y] in T, and 16-bit
-// copies of P and P^T in H (negative rounding residues clamped to 0 before the cast).
+// copies of P and P^T in H (negative rounding residues clamped to 0 before the cast); for
+// BF16 a lo part (value - hi) follows lo_off elements later.
 template <typename T, typename H>
-__global__ void __launch_bounds__(256)
-pmat_kernel(const double* __restrict__ eig, const double* __restrict__ cat_r,
-            const int32_t* __restrict__ idx, const double* __restrict__ t, int K, int S, int S_pad,
-            T* __restrict__ mats, T* __restrict__ tiptab, T* __restrict__ matsT, H* __restrict__ m16,
-            H* __restrict__ mT16, size_t lo_off, int32_t* __restrict__ status) {
+__device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const int k, const double tt) {
     __shared__ double W[kMaxStates * kMaxStates];  // W[j][y] = exp(lam_j r t) Vinv[j][y]
     __shared__ double rs[kMaxStates];              // rs[j] = exp(lam_j r t) sum_y Vinv[j][y]
-    const int i = blockIdx.x, k = blockIdx.y;
-    const int m = idx ? idx[i] : i;
-    const double tt = t[i];
+    const int K = d.K, S = d.S, S_pad = d.S_pad;
+    const int m = d.idx ? d.idx[i] : i;
     const bool bad = !(tt >= 0.0) || isinf(tt);
-    if (bad && threadIdx.x == 0) atomicOr(status, kStatusValue);
-    const double rt = cat_r[k] * tt;
-    const double* V = eig;
-    const double* Vi = eig + S * S;
-    const double* lam = eig + 2 * S * S;
+    if (bad && threadIdx.x == 0) atomicOr(d.status, kStatusValue);
+    const double rt = d.cat_r[k] * tt;
+    const double* V = d.eig;
+    const double* Vi = d.eig + S * S;
+    const double* lam = d.eig + 2 * S * S;
     for (int e = threadIdx.x; e < S * S; e += blockDim.x) {
         const int j = e / S;
         W[e] = exp(lam[j] * rt) * Vi[e];
@@ -47,8 +42,13 @@ pmat_kernel(const double* __restrict__ eig, const double* __restrict__ cat_r,
         rs[j] = s;
     }
     __syncthreads();
-    T* Pm = mats + (size_t)(m * K + k) * S_pad * S_pad;
-    T* Tt = tiptab + (size_t)(m * K + k) * (S + 1) * S_pad;
+    T* mats = static_cast<T*>(d.mats);
+    T* matsT = static_cast<T*>(d.matsT);
+    H* m16 = static_cast<H*>(d.m16);
+    H* mT16 = static_cast<H*>(d.mT16);
+    const size_t base = (size_t)(m * K + k) * S_pad * S_pad;
+    T* Pm = mats + base;
+    T* Tt = static_cast<T*>(d.tiptab) + (size_t)(m * K + k) * (S + 1) * S_pad;
     for (int e = threadIdx.x; e < S_pad * S_pad; e += blockDim.x) {
         const int x = e / S_pad, y = e % S_pad;
         double v = 0.0;
@@ -57,18 +57,16 @@ pmat_kernel(const double* __restrict__ eig, const double* __restrict__ cat_r,
         if (bad) v = NAN;
         Pm[e] = T(v);
         if (y < S) Tt[y * S_pad + x] = T(v);
-        const size_t base = (size_t)(m * K + k) * S_pad * S_pad;
         if (matsT) matsT[base + (size_t)y * S_pad + x] = T(v);
         if (m16) {
-            // hi part at base, lo part (value - hi, BF16 only) one full matrix array later
             const float c = v > 0.0 ? float(v) : (bad ? float(v) : 0.0f);
             const H hi = H(c);
-            const H lo = lo_off ? H(c - float(hi)) : H(0.0f);
             m16[base + e] = hi;
             mT16[base + (size_t)y * S_pad + x] = hi;
-            if (lo_off) {
-                m16[lo_off + base + e] = lo;
-                mT16[lo_off + base + (size_t)y * S_pad + x] = lo;
+            if (d.lo_off) {
+                const H lo = H(c - float(hi));
+                m16[d.lo_off + base + e] = lo;
+                mT16[d.lo_off + base + (size_t)y * S_pad + x] = lo;
             }
         }
     }
@@ -79,6 +77,19 @@ pmat_kernel(const double* __restrict__ eig, const double* __restrict__ cat_r,
         if (bad) v = NAN;
         Tt[S * S_pad + x] = T(v);
     }
+}
+
+template <typename T, typename H>
+__global__ void __launch_bounds__(256) pmat_kernel(const PmatDev d, const double* __restrict__ t) {
+    pmat_body<T, H>(d, blockIdx.x, blockIdx.y, t[blockIdx.x]);
+}
+
+template <typename T, typename H>
+__global__ void __launch_bounds__(256) pmat_batched(const BatchArgs b) {
+    const int q = batch_find(b.pmat_off, b.n, blockIdx.x);
+    const PmatDev d = load_desc<PmatDev>(b.pmat[q]);
+    const int i = blockIdx.x - b.pmat_off[q];
+    pmat_body<T, H>(d, i, blockIdx.y, b.t[q][i]);
 }
 
 // out[j] = sum_b partials[j][b] in a fixed order (strided per-thread sums, then a fixed
@@ -94,6 +105,22 @@ reduce_rows(const double* __restrict__ partials, int n_blocks, int first, double
     if ((threadIdx.x % kWave) == 0) ws[threadIdx.x / kWave] = s;
     __syncthreads();
     if (threadIdx.x == 0) out[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+// Batched second-stage reduction: block -> (instance, slot); the instance's reduction rows
+// come from the head of its traversal descriptor.
+__global__ void __launch_bounds__(256) reduce_batched(const BatchArgs b) {
+    __shared__ double ws[4];
+    const int q = batch_find(b.red_off, b.n, blockIdx.x);
+    const DescHead h = load_desc<DescHead>(b.walk[q]);
+    const int j = blockIdx.x - b.red_off[q];
+    double s = 0.0;
+    for (int blk = threadIdx.x; blk < h.n_blocks; blk += blockDim.x) s += h.partials[(size_t)j * h.n_blocks + blk];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if ((threadIdx.x % kWave) == 0) ws[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) b.out[q][j] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
 template <typename T>
@@ -114,40 +141,80 @@ hipError_t fill(const Instance& I, T* p, T v, size_t n) {
 
 }  // namespace
 
+PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx) {
+    const Layout& L = I.L;
+    PmatDev d{};
+    d.eig = I.at<double>(L.eig) + (size_t)eigen_idx * L.eig_stride;
+    d.cat_r = I.at<double>(L.cat_d);
+    d.idx = d_idx;
+    d.mats = I.ws + L.mats;
+    d.tiptab = I.ws + L.tiptab;
+    d.matsT = L.matsT ? I.ws + L.matsT : nullptr;
+    d.m16 = L.mats16 ? I.ws + L.mats16 : nullptr;
+    d.mT16 = L.matsT16 ? I.ws + L.matsT16 : nullptr;
+    d.lo_off = I.d.precision == HP_PREC_BF16 ? (size_t)I.d.n_matrices * L.mat_stride : 0;
+    d.status = I.at<int32_t>(L.status);
+    d.K = I.d.n_categories;
+    d.S = I.d.n_states;
+    d.S_pad = I.S_pad;
+    return d;
+}
+
 hipError_t launch_pmat(const Instance& I, int eigen_idx, const int32_t* d_idx, const double* d_t,
                        int count) {
     if (count <= 0) return hipSuccess;
-    const Layout& L = I.L;
-    const double* eig = I.at<double>(L.eig) + (size_t)eigen_idx * L.eig_stride;
+    const PmatDev d = build_pmat_desc(I, eigen_idx, d_idx);
     dim3 grid(count, I.d.n_categories), block(256);
-    const int S = I.d.n_states;
-    const int32_t* di = d_idx;
-    int32_t* st = I.at<int32_t>(L.status);
-    const double* cr = I.at<double>(L.cat_d);
-    const int K = I.d.n_categories, Sp = I.S_pad;
-    const size_t lo_all = (size_t)I.d.n_matrices * L.mat_stride;  // elements per 16-bit array
     switch (I.d.precision) {
         case HP_PREC_F64:
-            hipLaunchKernelGGL((pmat_kernel<double, _Float16>), grid, block, 0, I.stream, eig, cr, di, d_t,
-                               K, S, Sp, I.at<double>(L.mats), I.at<double>(L.tiptab),
-                               L.matsT ? I.at<double>(L.matsT) : nullptr, nullptr, nullptr, 0, st);
+            hipLaunchKernelGGL((pmat_kernel<double, _Float16>), grid, block, 0, I.stream, d, d_t);
             break;
         case HP_PREC_F32:
-            hipLaunchKernelGGL((pmat_kernel<float, _Float16>), grid, block, 0, I.stream, eig, cr, di, d_t,
-                               K, S, Sp, I.at<float>(L.mats), I.at<float>(L.tiptab),
-                               L.matsT ? I.at<float>(L.matsT) : nullptr, nullptr, nullptr, 0, st);
+            hipLaunchKernelGGL((pmat_kernel<float, _Float16>), grid, block, 0, I.stream, d, d_t);
             break;
         case HP_PREC_BF16:
-            hipLaunchKernelGGL((pmat_kernel<float, __bf16>), grid, block, 0, I.stream, eig, cr, di, d_t,
-                               K, S, Sp, I.at<float>(L.mats), I.at<float>(L.tiptab), I.at<float>(L.matsT),
-                               I.at<__bf16>(L.mats16), I.at<__bf16>(L.matsT16), lo_all, st);
+            hipLaunchKernelGGL((pmat_kernel<float, __bf16>), grid, block, 0, I.stream, d, d_t);
             break;
         default:
-            hipLaunchKernelGGL((pmat_kernel<float, _Float16>), grid, block, 0, I.stream, eig, cr, di, d_t,
-                               K, S, Sp, I.at<float>(L.mats), I.at<float>(L.tiptab), I.at<float>(L.matsT),
-                               I.at<_Float16>(L.mats16), I.at<_Float16>(L.matsT16), 0, st);
+            hipLaunchKernelGGL((pmat_kernel<float, _Float16>), grid, block, 0, I.stream, d, d_t);
             break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_small(const Instance& I, const WalkArgs& w);
+size_t build_tree_desc_small(const Instance& I, const WalkArgs& w, void* host_buf);
+hipError_t launch_batch_small(const Instance& I, const BatchArgs& b, int want_grad);
+size_t build_tree_desc_mfma(const Instance& I, const WalkArgs& w, void* host_buf);
+hipError_t launch_batch_mfma(const Instance& I, const BatchArgs& b, int want_grad);
+
+size_t build_tree_desc(const Instance& I, int want_grad, void* host_buf) {
+    const int N = I.d.n_tips;
+    WalkArgs a;
+    a.mode = want_grad ? (kPost | kRootFused | kPre | kGrad) : (kPost | kRootFused);
+    a.post_ops = I.at<int32_t>(I.L.tree_ops);
+    a.n_post = N - 1;
+    a.pre_ops = a.post_ops + (size_t)(N - 1) * kPostOpInts;
+    a.n_pre = want_grad ? N - 1 : 0;
+    a.n_grad = want_grad ? 2 * N - 2 : 0;
+    if (I.S_pad == 4) return build_tree_desc_small(I, a, host_buf);
+    return build_tree_desc_mfma(I, a, host_buf);
+}
+
+hipError_t launch_batch(const Instance& I, const BatchArgs& b, int want_grad) {
+    if (b.n <= 0) return hipSuccess;
+    dim3 gp(b.pmat_off[b.n], I.d.n_categories);
+    switch (I.d.precision) {
+        case HP_PREC_F64: hipLaunchKernelGGL((pmat_batched<double, _Float16>), gp, dim3(256), 0, I.stream, b); break;
+        case HP_PREC_F32: hipLaunchKernelGGL((pmat_batched<float, _Float16>), gp, dim3(256), 0, I.stream, b); break;
+        case HP_PREC_BF16: hipLaunchKernelGGL((pmat_batched<float, __bf16>), gp, dim3(256), 0, I.stream, b); break;
+        default: hipLaunchKernelGGL((pmat_batched<float, _Float16>), gp, dim3(256), 0, I.stream, b); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = I.S_pad == 4 ? launch_batch_small(I, b, want_grad) : launch_batch_mfma(I, b, want_grad);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_batched, dim3(b.red_off[b.n]), dim3(256), 0, I.stream, b);
     return hipGetLastError();
 }
 

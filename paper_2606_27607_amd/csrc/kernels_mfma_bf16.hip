@@ -3,4 +3,10 @@
 
 namespace hp {
 hipError_t launch_walk_mfma_bf16(const Instance& I, const WalkArgs& w) { return dispatch_precision<HP_PREC_BF16>(I, w); }
+size_t build_tree_desc_mfma_bf16(const Instance& I, const WalkArgs& w, void* buf) {
+    return desc_precision<HP_PREC_BF16>(I, w, buf);
+}
+hipError_t launch_batch_mfma_bf16(const Instance& I, const BatchArgs& b, int want_grad) {
+    return batch_precision<HP_PREC_BF16>(I, b, want_grad);
+}
 }  // namespace hp

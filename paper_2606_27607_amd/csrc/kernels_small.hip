@@ -102,6 +102,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 template <typename T>
 struct WalkDev {
+    DescHead h;             // partials [n_out][n_blocks], n_blocks, n_out (read by batched reduce)
     const uint8_t* tips;    // [N][P_pad]
     const double* pw;       // [P_pad]
     T* post;                // [n_partials][K][P_pad][4]
@@ -116,10 +117,9 @@ struct WalkDev {
     const int32_t* post_ops;
     const int32_t* pre_ops;
     double* site;           // [P_pad] or null
-    double* partials;       // [n_out][n_blocks]
     int32_t* status;
     size_t stride;          // elements per partial buffer
-    int n_post, n_pre, root_buf, n_out, n_blocks;
+    int n_post, n_pre, root_buf;
     int N, P_pad, K, S, rescale_pre;
 };
 
@@ -140,18 +140,18 @@ __device__ __forceinline__ int child_exp(const WalkDev<T>& a, int c, int p) {
 }
 
 template <typename T, int KMAX, int MODE>
-__global__ void __launch_bounds__(KMAX * kWave) walk_small(const WalkDev<T> a) {
+__device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int block) {
     __shared__ int sh_e[2][2][KMAX][kWave];
     __shared__ T sh_v[2][3][KMAX][kWave];
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    const int p = blockIdx.x * kWave + lane;
+    const int p = block * kWave + lane;
     const int K = a.K;
     int sb = 0;  // exchange counter: consecutive LDS exchanges alternate buffers
 
     if (MODE & (kRootFused | kRootBuf | kGrad)) {
-        for (int j = threadIdx.x; j < a.n_out; j += blockDim.x)
-            a.partials[(size_t)j * a.n_blocks + blockIdx.x] = 0.0;
+        for (int j = threadIdx.x; j < a.h.n_out; j += blockDim.x)
+            a.h.partials[(size_t)j * a.h.n_blocks + block] = 0.0;
         __syncthreads();
     }
 
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(KMAX * kWave) walk_small(const WalkDev<T> a) {
             if (a.site) a.site[p] = l;
             const double w = a.pw[p];
             double tot = wave_sum(w == 0.0 ? 0.0 : w * l);
-            if (lane == 0) a.partials[blockIdx.x] = tot;
+            if (lane == 0) a.h.partials[block] = tot;
         }
     };
 
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(KMAX * kWave) walk_small(const WalkDev<T> a) {
                             num += double(sh_v[s][1 + side][kk][lane]);
                         }
                         const double tot = wave_sum(cp == 0.0 ? 0.0 : cp * (num / den));
-                        if (lane == 0) a.partials[(size_t)(1 + g) * a.n_blocks + blockIdx.x] = tot;
+                        if (lane == 0) a.h.partials[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
                     }
                 }
             }
@@ -279,8 +279,21 @@ __global__ void __launch_bounds__(KMAX * kWave) walk_small(const WalkDev<T> a) {
     }
 }
 
-template <typename T, int KMAX>
-hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
+template <typename T, int KMAX, int MODE>
+__global__ void __launch_bounds__(KMAX * kWave) walk_small(const WalkDev<T> a) {
+    walk_small_body<T, KMAX, MODE>(a, blockIdx.x);
+}
+
+// One launch over the tiles of several instances: block -> (instance, local block).
+template <typename T, int KMAX, int MODE>
+__global__ void __launch_bounds__(KMAX * kWave) walk_small_batched(const BatchArgs b) {
+    const int i = batch_find(b.walk_off, b.n, blockIdx.x);
+    const WalkDev<T> a = load_desc<WalkDev<T>>(b.walk[i]);
+    walk_small_body<T, KMAX, MODE>(a, blockIdx.x - b.walk_off[i]);
+}
+
+template <typename T>
+WalkDev<T> make_desc(const Instance& I, const WalkArgs& w) {
     const Layout& L = I.L;
     WalkDev<T> a{};
     a.tips = I.at<uint8_t>(L.tips);
@@ -297,19 +310,25 @@ hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
     a.post_ops = w.post_ops;
     a.pre_ops = w.pre_ops;
     a.site = w.site;
-    a.partials = I.at<double>(L.partials);
+    a.h.partials = I.at<double>(L.partials);
     a.status = I.at<int32_t>(L.status);
     a.stride = L.post_stride;
     a.n_post = w.n_post;
     a.n_pre = w.n_pre;
     a.root_buf = w.root_buf;
-    a.n_out = 1 + w.n_grad;
-    a.n_blocks = I.n_blocks;
+    a.h.n_out = 1 + w.n_grad;
+    a.h.n_blocks = I.n_blocks;
     a.N = I.d.n_tips;
     a.P_pad = I.P_pad;
     a.K = I.d.n_categories;
     a.S = I.d.n_states;
     a.rescale_pre = I.d.scaling != HP_SCALE_NONE;
+    return a;
+}
+
+template <typename T, int KMAX>
+hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
+    const WalkDev<T> a = make_desc<T>(I, w);
     dim3 grid(I.n_blocks), block(kWave * I.d.n_categories);
 #define HP_LAUNCH(M) hipLaunchKernelGGL((walk_small<T, KMAX, M>), grid, block, 0, I.stream, a)
     switch (w.mode) {
@@ -325,7 +344,36 @@ hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
     return hipGetLastError();
 }
 
+template <typename T, int KMAX>
+hipError_t dispatch_batch(const Instance& I, const BatchArgs& b, int want_grad) {
+    dim3 grid(b.walk_off[b.n]), block(kWave * I.d.n_categories);
+    if (want_grad)
+        hipLaunchKernelGGL((walk_small_batched<T, KMAX, kPost | kRootFused | kPre | kGrad>), grid, block, 0,
+                           I.stream, b);
+    else
+        hipLaunchKernelGGL((walk_small_batched<T, KMAX, kPost | kRootFused>), grid, block, 0, I.stream, b);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+size_t build_tree_desc_small(const Instance& I, const WalkArgs& w, void* host_buf) {
+    if (I.d.precision == HP_PREC_F64) {
+        const WalkDev<double> a = make_desc<double>(I, w);
+        std::memcpy(host_buf, &a, sizeof(a));
+        return sizeof(a);
+    }
+    const WalkDev<float> a = make_desc<float>(I, w);
+    std::memcpy(host_buf, &a, sizeof(a));
+    return sizeof(a);
+}
+
+hipError_t launch_batch_small(const Instance& I, const BatchArgs& b, int want_grad) {
+    const bool f64 = I.d.precision == HP_PREC_F64;
+    if (I.d.n_categories <= 4)
+        return f64 ? dispatch_batch<double, 4>(I, b, want_grad) : dispatch_batch<float, 4>(I, b, want_grad);
+    return f64 ? dispatch_batch<double, 8>(I, b, want_grad) : dispatch_batch<float, 8>(I, b, want_grad);
+}
 
 hipError_t launch_walk_small(const Instance& I, const WalkArgs& w) {
     const bool f64 = I.d.precision == HP_PREC_F64;

@@ -1,0 +1,436 @@
+"""Serving: continuous batching of lnL + gradient requests from many MCMC / optimiser clients.
+
+Each client registers a data set (tips, pattern weights, model, tree) once and then submits
+branch-length vectors; every request returns lnL and all 2N-2 branch gradients.
+
+* Sessions keep their instance (partial buffers, matrices, tip states) resident on the
+  device between requests.  A session is admitted only if its workspace fits the device
+  memory budget; idle sessions are evicted least-recently-used to make room, and a request
+  whose session cannot be admitted waits.
+* A data set larger than the per-session cap is split into pattern chunks (patterns are
+  conditionally independent given the tree and model); each chunk is its own sub-session
+  and the request's result is the sum over chunks, taken in chunk order.
+* A scheduler thread forms batches continuously: requests that arrive while earlier batches
+  run are admitted as soon as memory and their session are free, and up to HP_MAX_BATCH
+  sessions of one class (precision, state padding, categories) are evaluated by a single
+  launch per kernel (hp_batch_evaluate_device) on that class's stream; several batches per
+  class may be in flight and different classes overlap on the device.
+* Latency is measured from submission to result (p50 / p99), beside throughput.
+* A malformed request (wrong length, negative or non-finite branch length) fails with
+  HP_ERR_VALUE on its own future; an error reported by the device for one session fails
+  only that session's request; the loop keeps serving everyone else.
+
+Results do not depend on what else is batched or running: the batched kernels run the same
+per-instance arithmetic with fixed-order reductions, so a result is bitwise the same alone
+and in the mix.
+
+All device work goes through an executor (`HipExecutor`); the scheduling logic itself is
+plain Python and is tested on the CPU with a stand-in executor.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+
+DEFAULT_PRECISION = {4: "f32"}   # larger state spaces default to "bf16"
+MAX_BATCH = 32                   # HP_MAX_BATCH
+
+
+@dataclass
+class Dataset:
+    tips: np.ndarray          # uint8 [N, P]
+    weights: np.ndarray       # float64 [P]
+    V: np.ndarray
+    Vinv: np.ndarray
+    lam: np.ndarray
+    pi: np.ndarray
+    rates: np.ndarray
+    cat_weights: np.ndarray
+    children: np.ndarray      # int [2N-1, 2]
+
+    @property
+    def n_tips(self):
+        return self.tips.shape[0]
+
+    @property
+    def n_patterns(self):
+        return self.tips.shape[1]
+
+    @property
+    def n_states(self):
+        return self.pi.shape[0]
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
+                   wl.tree.children)
+
+    def chunk(self, lo, hi):
+        return Dataset(np.ascontiguousarray(self.tips[:, lo:hi]), self.weights[lo:hi], self.V,
+                       self.Vinv, self.lam, self.pi, self.rates, self.cat_weights, self.children)
+
+
+def scaling_for(n_states):
+    return ("every_k", 4) if n_states <= 4 else ("every_node", 1)
+
+
+class HipExecutor:
+    """Device side of the server: instances, batched launches on per-class streams."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = _lib.load()
+        self.device_index = device
+        self.device = torch.device("cuda", device)
+        self.streams = {}
+
+    def free_memory(self):
+        free, _ = self.torch.cuda.mem_get_info(self.device)
+        return free
+
+    def footprint(self, data: Dataset, precision: str) -> int:
+        sc = scaling_for(data.n_states)
+        d = _lib.hp_desc(n_tips=data.n_tips, n_patterns=data.n_patterns, n_states=data.n_states,
+                         n_categories=len(data.rates), n_partials=data.n_tips - 1,
+                         n_matrices=2 * data.n_tips - 2, n_eigen=1,
+                         precision=_lib.PRECISIONS[precision], scaling=_lib.SCALINGS[sc[0]],
+                         scale_period=sc[1], device=self.device_index)
+        n = ctypes.c_size_t()
+        _lib.check(self.lib, self.lib.hp_workspace_bytes(ctypes.byref(d), ctypes.byref(n)))
+        return n.value
+
+    def load(self, s):
+        torch = self.torch
+        from .instance import Instance
+        d = s.data
+        sc = scaling_for(d.n_states)
+        inst = Instance(d.n_tips, d.n_patterns, d.n_states, len(d.rates), precision=s.precision,
+                        scaling=sc[0], scale_period=sc[1], device=self.device_index)
+        inst.load(d.tips, d.weights, d.V, d.Vinv, d.lam, d.pi, d.rates, d.cat_weights,
+                  children=d.children)
+        nb = 2 * d.n_tips - 2
+        s.state = {"inst": inst,
+                   "t_dev": torch.empty(nb, dtype=torch.float64, device=self.device),
+                   "out_dev": torch.empty(1 + nb, dtype=torch.float64, device=self.device),
+                   "t_host": torch.empty(nb, dtype=torch.float64, pin_memory=True),
+                   "out_host": torch.empty(1 + nb, dtype=torch.float64, pin_memory=True)}
+        return (s.precision, inst.query(_lib.HP_Q_STATE_PAD), len(d.rates))
+
+    def evict(self, s):
+        if s.state is not None:
+            s.state["inst"].close()
+        s.state = None
+
+    def launch(self, key, items):
+        """items: [(session, t)].  Enqueue one batched evaluation; return a completion token."""
+        torch = self.torch
+        stream = self.streams.get(key)
+        if stream is None:
+            stream = self.streams[key] = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(stream):
+            for s, t in items:
+                st = s.state
+                st["t_host"].numpy()[:] = t
+                st["t_dev"].copy_(st["t_host"], non_blocking=True)
+            n = len(items)
+            insts = (ctypes.c_void_p * n)(*[s.state["inst"]._inst.value for s, _ in items])
+            tp = (ctypes.c_void_p * n)(*[s.state["t_dev"].data_ptr() for s, _ in items])
+            op = (ctypes.c_void_p * n)(*[s.state["out_dev"].data_ptr() for s, _ in items])
+            rc = self.lib.hp_batch_evaluate_device(insts, tp, op, n, 1, ctypes.c_void_p(stream.cuda_stream))
+            if rc != _lib.HP_OK:
+                raise _lib.HPError(rc, _lib.last_error(self.lib, None))
+            for s, _ in items:
+                s.state["out_host"].copy_(s.state["out_dev"], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return (ev, items)
+
+    def poll(self, token):
+        """None while running; then [(ok, result or exception)] per item."""
+        ev, items = token
+        if not ev.query():
+            return None
+        res = []
+        for s, _ in items:
+            try:
+                s.state["inst"].status()
+                res.append((True, s.state["out_host"].numpy().copy()))
+            except Exception as e:  # noqa: BLE001 - reported on that request only
+                res.append((False, e))
+        return res
+
+
+class _Session:
+    """One admitted-or-evictable unit: a client's data set or one pattern chunk of it."""
+
+    def __init__(self, client, chunk, data: Dataset, precision, footprint):
+        self.client = client
+        self.chunk = chunk
+        self.data = data
+        self.precision = precision
+        self.footprint = footprint
+        self.state = None          # executor's resident state (None: not on the device)
+        self.key = None
+        self.busy = False
+        self.last_used = 0.0
+
+    @property
+    def resident(self):
+        return self.state is not None
+
+
+@dataclass
+class _Request:
+    client: int
+    t: np.ndarray
+    arrival: float
+    future: Future
+    parts: dict = field(default_factory=dict)     # chunk -> out (lnL, grads)
+    remaining: int = 0
+
+
+class Server:
+    """Continuous-batching request loop on one device.
+
+    memory_budget: bytes of device memory the sessions' workspaces may occupy (default: 85 %
+    of the device's free memory at start-up); max_session_bytes: data sets whose workspace
+    exceeds this are split into pattern chunks (default: a quarter of the budget).
+    """
+
+    def __init__(self, device: int = 0, memory_budget: int | None = None,
+                 max_session_bytes: int | None = None, max_batch: int = MAX_BATCH,
+                 max_inflight_per_class: int = 2, precision: dict | None = None, executor=None):
+        self.ex = executor if executor is not None else HipExecutor(device)
+        if memory_budget is None:
+            memory_budget = int(0.85 * self.ex.free_memory())
+        self.memory_budget = int(memory_budget)
+        self.max_session_bytes = int(max_session_bytes or self.memory_budget // 4)
+        self.max_batch = max(1, min(int(max_batch), MAX_BATCH))
+        self.max_inflight = max(1, int(max_inflight_per_class))
+        self.precision = dict(DEFAULT_PRECISION)
+        self.precision.update(precision or {})
+        self.sessions = {}                          # client -> [chunk sessions]
+        self.used = 0
+        self.pending = collections.OrderedDict()    # session -> deque of requests
+        self.inflight = []                          # (token, key, [(session, request)])
+        self.cv = threading.Condition()
+        self.incoming = collections.deque()
+        self.running = False
+        self.thread = None
+        self.latencies = []
+        self.completed = 0
+        self.errors = 0
+        self.batches = 0
+        self.batch_sizes = []
+        self.evictions = 0
+        self.max_concurrent_batches = 0
+        self.t_first = None
+        self.t_last = None
+
+    # ------------------------------------------------------------------ clients
+    def register(self, client, data: Dataset, precision: str | None = None) -> int:
+        prec = precision or self.precision.get(data.n_states, "bf16")
+        full = self.ex.footprint(data, prec)
+        n_chunks = max(1, -(-full // self.max_session_bytes))
+        if n_chunks > data.n_patterns:
+            raise ValueError(f"client {client}: cannot chunk {data.n_patterns} patterns into {n_chunks}")
+        bounds = np.linspace(0, data.n_patterns, n_chunks + 1).astype(int)
+        sess = []
+        for c in range(n_chunks):
+            d = data if n_chunks == 1 else data.chunk(bounds[c], bounds[c + 1])
+            fp = full if n_chunks == 1 else self.ex.footprint(d, prec)
+            if fp > self.memory_budget:
+                raise ValueError(f"client {client}: a pattern chunk does not fit the memory budget")
+            sess.append(_Session(client, c, d, prec, fp))
+        with self.cv:
+            self.sessions[client] = sess
+        return n_chunks
+
+    def submit(self, client, t) -> Future:
+        fut = Future()
+        with self.cv:
+            if client not in self.sessions:
+                raise KeyError(f"client {client} is not registered")
+            nb = 2 * self.sessions[client][0].data.n_tips - 2
+        t = np.asarray(t, dtype=np.float64).ravel()
+        if t.size != nb or not np.all(np.isfinite(t)) or np.any(t < 0):
+            fut.set_exception(_lib.HPError(_lib.HP_ERR_VALUE,
+                                           f"client {client}: need {nb} finite non-negative branch lengths"))
+            with self.cv:
+                self.errors += 1
+            return fut
+        req = _Request(client, np.ascontiguousarray(t), time.perf_counter(), fut)
+        with self.cv:
+            self.incoming.append(req)
+            self.cv.notify()
+        return fut
+
+    def evaluate(self, client, t):
+        """Synchronous convenience: submit and wait for (lnL, gradients)."""
+        return self.submit(client, t).result()
+
+    # ------------------------------------------------------------------ lifecycle
+    def start(self):
+        if not self.running:
+            self.running = True
+            self.thread = threading.Thread(target=self._loop, name="hipphylo-serve", daemon=True)
+            self.thread.start()
+        return self
+
+    def stop(self):
+        """Finish every submitted request, then stop the scheduler thread."""
+        with self.cv:
+            self.running = False
+            self.cv.notify()
+        if self.thread is not None:
+            self.thread.join()
+        self.thread = None
+
+    def close(self):
+        self.stop()
+        for sess in self.sessions.values():
+            for s in sess:
+                if s.resident:
+                    self.ex.evict(s)
+        self.used = 0
+
+    def __enter__(self):
+        return self.start()
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def stats(self):
+        lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        span = (self.t_last - self.t_first) if self.completed else 0.0
+        return {"completed": self.completed, "errors": self.errors, "batches": self.batches,
+                "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+                "max_concurrent_batches": self.max_concurrent_batches,
+                "evictions": self.evictions,
+                "p50_ms": 1000 * float(np.percentile(lat, 50)),
+                "p99_ms": 1000 * float(np.percentile(lat, 99)),
+                "mean_ms": 1000 * float(np.mean(lat)),
+                "requests_per_s": self.completed / span if span > 0 else float("nan"),
+                "memory_used": self.used, "memory_budget": self.memory_budget}
+
+    # ------------------------------------------------------------------ scheduler (one thread)
+    def _loop(self):
+        while True:
+            with self.cv:
+                while self.incoming:
+                    req = self.incoming.popleft()
+                    sess = self.sessions[req.client]
+                    req.remaining = len(sess)
+                    for s in sess:
+                        self.pending.setdefault(s, collections.deque()).append(req)
+                if not self.running and not self.pending and not self.inflight:
+                    return
+                if not self.pending and not self.inflight:
+                    self.cv.wait(timeout=0.01)
+                    continue
+            progressed = self._complete()
+            progressed |= self._dispatch()
+            if not progressed:
+                time.sleep(50e-6)
+
+    def _admit(self, s: _Session) -> bool:
+        if s.resident:
+            return True
+        if self.used + s.footprint > self.memory_budget:
+            idle = [x for sess in self.sessions.values() for x in sess
+                    if x.resident and not x.busy and not self.pending.get(x)]
+            idle.sort(key=lambda x: x.last_used)
+            need = self.used + s.footprint - self.memory_budget
+            victims, freed = [], 0
+            for x in idle:
+                if freed >= need:
+                    break
+                victims.append(x)
+                freed += x.footprint
+            if freed < need:
+                return False
+            for x in victims:
+                self.ex.evict(x)
+                self.used -= x.footprint
+                self.evictions += 1
+        s.key = self.ex.load(s)
+        self.used += s.footprint
+        return True
+
+    def _dispatch(self) -> bool:
+        launched = False
+        by_class = collections.defaultdict(list)
+        for s in [s for s, q in self.pending.items() if q and not s.busy]:
+            if self._admit(s):
+                by_class[s.key].append(s)
+        for key, group in by_class.items():
+            if sum(1 for b in self.inflight if b[1] == key) >= self.max_inflight:
+                continue
+            group.sort(key=lambda s: self.pending[s][0].arrival)
+            items = []
+            for s in group[: self.max_batch]:
+                req = self.pending[s].popleft()
+                s.busy = True
+                items.append((s, req))
+            try:
+                token = self.ex.launch(key, [(s, req.t) for s, req in items])
+            except Exception as e:  # noqa: BLE001 - fail this batch's requests only
+                for s, req in items:
+                    s.busy = False
+                    self._fail(req, e)
+                continue
+            self.inflight.append((token, key, items))
+            self.max_concurrent_batches = max(self.max_concurrent_batches, len(self.inflight))
+            self.batches += 1
+            self.batch_sizes.append(len(items))
+            launched = True
+        for s in [s for s, q in self.pending.items() if not q]:
+            del self.pending[s]
+        return launched
+
+    def _fail(self, req, err):
+        if not req.future.done():
+            req.future.set_exception(err)
+            self.errors += 1
+
+    def _complete(self) -> bool:
+        done_any = False
+        still = []
+        for token, key, items in self.inflight:
+            res = self.ex.poll(token)
+            if res is None:
+                still.append((token, key, items))
+                continue
+            done_any = True
+            now = time.perf_counter()
+            for (s, req), (ok, val) in zip(items, res):
+                s.busy = False
+                s.last_used = now
+                if not ok:
+                    self._fail(req, val)
+                    continue
+                req.parts[s.chunk] = val
+                req.remaining -= 1
+                if req.remaining == 0 and not req.future.done():
+                    out = req.parts[0].copy()
+                    for c in range(1, len(req.parts)):
+                        out += req.parts[c]
+                    req.future.set_result((float(out[0]), out[1:]))
+                    self.latencies.append(now - req.arrival)
+                    self.completed += 1
+                    self.t_first = req.arrival if self.t_first is None else min(self.t_first, req.arrival)
+                    self.t_last = now
+        self.inflight = still
+        return done_any
+
+
+__all__ = ["Server", "Dataset", "HipExecutor"]

@@ -1,0 +1,119 @@
+"""Serving on the GPU: batched launches and the continuous-batching server give each request
+the same result alone and in the mix (bitwise), under memory pressure and with chunking."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import announce, grad_err, make_instance, oracle_eval, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _mixed_workloads():
+    specs = [("gtr", 17, 900, 1), ("gtr", 40, 130, 2), ("gtr", 5, 5000, 3), ("hky", 64, 64, 4),
+             ("gy94", 9, 300, 5), ("gy94", 30, 77, 6), ("aa", 12, 500, 7), ("aa", 3, 40, 8)]
+    return [synth.make_workload(k, n, p, seed=s, unknown_frac=0.03) for k, n, p, s in specs]
+
+
+@pytest.mark.parametrize("cls", ["nuc", "codon", "aa"])
+def test_batched_launch_equals_alone(cls):
+    import torch
+    from paper_2606_27607_amd import _lib
+    S = {"nuc": 4, "codon": 61, "aa": 20}[cls]
+    wls = [w for w in _mixed_workloads() if w.n_states == S]
+    prec, scaling = ("f32", ("every_k", 4)) if cls == "nuc" else ("bf16", ("every_node", 1))
+    insts = [make_instance(w, prec, *scaling) for w in wls]
+    ts = [torch.tensor(w.t[: 2 * w.n_tips - 2] * 1.1, dtype=torch.float64, device="cuda") for w in wls]
+    alone = [inst.evaluate_device(t).clone() for inst, t in zip(insts, ts)]
+    torch.cuda.synchronize()
+    outs = [torch.full((1 + 2 * w.n_tips - 2,), -1.0, dtype=torch.float64, device="cuda") for w in wls]
+    lib = _lib.load()
+    n = len(insts)
+    announce(f"batched launch of {n} instances ({cls})")
+    rc = lib.hp_batch_evaluate_device((ctypes.c_void_p * n)(*[i._inst.value for i in insts]),
+                                      (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts]),
+                                      (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs]), n, 1,
+                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0, _lib.last_error(lib, None)
+    torch.cuda.synchronize()
+    for inst, a, b in zip(insts, alone, outs):
+        inst.status()
+        assert torch.equal(a, b)
+
+
+def test_batch_rejects_mixed_classes():
+    import torch
+    from paper_2606_27607_amd import _lib
+    wls = _mixed_workloads()
+    a = make_instance(wls[0], "f32", "every_k", 4)
+    b = make_instance(wls[4], "bf16", "every_node")
+    t = torch.zeros(64, dtype=torch.float64, device="cuda")
+    lib = _lib.load()
+    rc = lib.hp_batch_evaluate_device((ctypes.c_void_p * 2)(a._inst.value, b._inst.value),
+                                      (ctypes.c_void_p * 2)(t.data_ptr(), t.data_ptr()),
+                                      (ctypes.c_void_p * 2)(t.data_ptr(), t.data_ptr()), 2, 1, None)
+    assert rc == _lib.HP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("budget_frac", [None, 0.35])
+def test_server_mix_equals_alone(budget_frac):
+    from paper_2606_27607_amd.serve import Dataset, HipExecutor, Server
+    wls = _mixed_workloads()
+    ex = HipExecutor(0)
+    prec = {4: "f32", 20: "bf16", 61: "f16"}
+    fps = [ex.footprint(Dataset.from_workload(w), prec[w.n_states]) for w in wls]
+    budget = None if budget_frac is None else int(budget_frac * sum(fps)) + max(fps)
+    rng = np.random.default_rng(11)
+    reqs = [(c, wls[c].t[: 2 * wls[c].n_tips - 2] * np.exp(0.05 * rng.standard_normal(2 * wls[c].n_tips - 2)))
+            for rep in range(3) for c in rng.permutation(len(wls))]
+    announce(f"server mix, budget {budget}")
+    # no pattern chunking here: a chunked session sums its chunks in chunk order, which is
+    # deterministic but rounds differently from one unchunked instance
+    with Server(memory_budget=budget or 8 << 30, max_session_bytes=budget or 8 << 30, executor=ex,
+                precision=prec) as srv:
+        for c, w in enumerate(wls):
+            srv.register(c, Dataset.from_workload(w))
+        futs = [srv.submit(c, t) for c, t in reqs]
+        results = [f.result(timeout=120) for f in futs]
+        st = srv.stats()
+    print(st)
+    if budget is not None:
+        assert st["evictions"] > 0
+    assert st["completed"] == len(reqs) and st["errors"] == 0
+    # alone: each request on a fresh instance of its own, one at a time
+    alone = {}
+    for c, w in enumerate(wls):
+        sc = ("every_k", 4) if w.n_states == 4 else ("every_node", 1)
+        alone[c] = make_instance(w, prec[w.n_states], *sc)
+    for (c, t), (lnl, g) in zip(reqs, results):
+        lnl_a, g_a = alone[c].evaluate(t)
+        assert lnl == lnl_a and np.array_equal(g, g_a), c
+    # and the mix is within tolerance of the FP64 oracle on one request per state space
+    for c in (0, 4, 6):
+        t = reqs[[r[0] for r in reqs].index(c)][1]
+        lnl, g = results[[r[0] for r in reqs].index(c)]
+        full_t = np.r_[t, 0.0]
+        lnl_o, _, g_o = oracle_eval(wls[c], t=full_t)
+        assert rel(lnl, lnl_o) < 1e-4 and grad_err(g, g_o) < 5e-2
+
+
+def test_chunked_session_matches_unchunked():
+    from paper_2606_27607_amd.serve import Dataset, HipExecutor, Server
+    wl = synth.make_workload("gtr", 24, 6000, seed=12)
+    ex = HipExecutor(0)
+    full = ex.footprint(Dataset.from_workload(wl), "f64")
+    with Server(memory_budget=full, max_session_bytes=full // 3 + 1, executor=ex,
+                precision={4: "f64"}) as srv:
+        assert srv.register(0, Dataset.from_workload(wl)) >= 3
+        lnl, g = srv.evaluate(0, wl.t[:46])
+    lnl_o, _, g_o = oracle_eval(wl)
+    assert rel(lnl, lnl_o) < 1e-12 and grad_err(g, g_o) < 1e-10
