@@ -752,6 +752,7 @@ static int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, doubl
     HP_HIP(I, HP_PMAT(*I, 0, nullptr, d_t, 2 * N - 2));
     hp::WalkArgs a;
     a.mode = want_grad ? (hp::kPost | hp::kRootFused | hp::kPre | hp::kGrad) : (hp::kPost | hp::kRootFused);
+    a.tree = true;
     a.post_ops = I->at<int32_t>(I->L.tree_ops);
     a.n_post = I->tree_n_post;
     a.pre_ops = a.post_ops + (size_t)(N - 1) * hp::kPostOpInts;
@@ -898,6 +899,7 @@ int hp_gradients_device(hp_instance* inst, double* d_grad) {
     DeviceGuard g(I->d.device);
     hp::WalkArgs a;
     a.mode = hp::kPre | hp::kGrad;
+    a.tree = true;
     a.pre_ops = I->at<int32_t>(I->L.tree_ops) + (size_t)(N - 1) * hp::kPostOpInts;
     a.n_pre = I->tree_n_pre;
     a.n_grad = 2 * N - 2;

@@ -179,6 +179,9 @@ struct WalkArgs {
     int eigen_idx = 0;
     int n_grad = 0;        // gradient slots; reduction rows hold 1 + n_grad values
     double* site = nullptr;
+    // whole-tree evaluation (hp_set_tree's lists): for 4 < S the post buffers then hold
+    // u_c = P_c post_c of each edge instead of post_c (see tree_mfma_body)
+    bool tree = false;
 };
 hipError_t launch_walk(const Instance& I, const WalkArgs& a);
 // Size in bytes of the traversal descriptor for whole-tree evaluation, written to host_buf.

@@ -192,6 +192,7 @@ size_t build_tree_desc(const Instance& I, int want_grad, void* host_buf) {
     const int N = I.d.n_tips;
     WalkArgs a;
     a.mode = want_grad ? (kPost | kRootFused | kPre | kGrad) : (kPost | kRootFused);
+    a.tree = true;
     a.post_ops = I.at<int32_t>(I.L.tree_ops);
     a.n_post = N - 1;
     a.pre_ops = a.post_ops + (size_t)(N - 1) * kPostOpInts;

@@ -121,22 +121,21 @@ struct WalkDev {
     size_t stride;          // elements per partial buffer
     int n_post, n_pre, root_buf;
     int N, P_pad, K, S, rescale_pre;
+    int tree;               // whole-tree lists: pre-order partials are read once (see below)
+};
+
+// What one child edge of an operation needs for the lane: its tip state, or its partial
+// and cumulative exponent.
+template <typename T>
+struct ChildIn {
+    V4<T> v;
+    int e;
+    int s;
 };
 
 template <typename T>
-__device__ __forceinline__ V4<T> child_u(const WalkDev<T>& a, int c, int m, int k, int p) {
-    if (c < a.N) {
-        int s = a.tips[(size_t)c * a.P_pad + p];
-        s = s > a.S ? a.S : s;
-        return ld4(a.tiptab + ((size_t)(m * a.K + k) * (a.S + 1) + s) * 4);
-    }
-    V4<T> v = ld4(a.post + (size_t)(c - a.N) * a.stride + ((size_t)k * a.P_pad + p) * 4);
-    return matvec(as_const(a.mats + (size_t)(m * a.K + k) * 16), v);
-}
-
-template <typename T>
-__device__ __forceinline__ int child_exp(const WalkDev<T>& a, int c, int p) {
-    return c < a.N ? 0 : a.pexp[(size_t)(c - a.N) * a.P_pad + p];
+__device__ __forceinline__ V4<T> prev_none() {
+    return V4<T>{};
 }
 
 template <typename T, int KMAX, int MODE>
@@ -174,12 +173,55 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
         }
     };
 
+    // Each operation's inputs that do not depend on the previous operation are loaded one
+    // operation ahead (prefetch), and an input that the previous operation produced is taken
+    // from registers (forwarding) instead of a store-load round trip.  Both keep the exact
+    // values memory would have returned, so results do not change.
+    auto post_ptr = [&](int c) { return a.post + (size_t)(c - a.N) * a.stride + ((size_t)k * a.P_pad + p) * 4; };
+    auto pre_ptr = [&](int q) { return a.pre + (size_t)q * a.stride + ((size_t)k * a.P_pad + p) * 4; };
+    // load what a child edge needs unless the child is `fwd` (produced by the operation before)
+    auto fetch = [&](int c, int fwd, ChildIn<T>& ci) {
+        if (c < a.N) {
+            ci.s = a.tips[(size_t)c * a.P_pad + p];
+        } else if (c != fwd) {
+            ci.v = ld4(post_ptr(c));
+            ci.e = a.pexp[(size_t)(c - a.N) * a.P_pad + p];
+        }
+    };
+    // u = P_m x for the child (x: tip column, forwarded or loaded partial) and its exponent
+    auto resolve = [&](int c, int m, const ChildIn<T>& ci, int fwd, const V4<T>& fx, int fe, int& e) {
+        if (c < a.N) {
+            e = 0;
+            const int st = ci.s > a.S ? a.S : ci.s;
+            return ld4(a.tiptab + ((size_t)(m * K + k) * (a.S + 1) + st) * 4);
+        }
+        const bool f = c == fwd;
+        e = f ? fe : ci.e;
+        return matvec(as_const(a.mats + (size_t)(m * K + k) * 16), f ? fx : ci.v);
+    };
+
     if (MODE & kPost) {
+        ChildIn<T> in1{}, in2{}, nx1{}, nx2{};
+        int prev = -1, prev_e = 0;
+        V4<T> prev_x{};
+        if (a.n_post > 0) {
+            cptr<int32_t> op0 = as_const(a.post_ops);
+            fetch(op0[1], -1, in1);
+            fetch(op0[3], -1, in2);
+        }
         for (int i = 0; i < a.n_post; ++i) {
             cptr<int32_t> op = as_const(a.post_ops + (size_t)i * kPostOpInts);
             const int dest = op[0], c1 = op[1], m1 = op[2], c2 = op[3], m2 = op[4], resc = op[5];
-            V4<T> x = mul(child_u(a, c1, m1, k, p), child_u(a, c2, m2, k, p));
-            int E = child_exp(a, c1, p) + child_exp(a, c2, p);
+            if (i + 1 < a.n_post) {
+                cptr<int32_t> on = as_const(a.post_ops + (size_t)(i + 1) * kPostOpInts);
+                fetch(on[1], dest, nx1);
+                fetch(on[3], dest, nx2);
+            }
+            int e1, e2;
+            const V4<T> u1 = resolve(c1, m1, in1, prev, prev_x, prev_e, e1);
+            const V4<T> u2 = resolve(c2, m2, in2, prev, prev_x, prev_e, e2);
+            V4<T> x = mul(u1, u2);
+            int E = e1 + e2;
             if (resc) {
                 const int s = (sb++) & 1;
                 sh_e[s][0][k][lane] = scale_exp(max4(x));
@@ -193,15 +235,19 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             if ((MODE & kRootFused) && i == a.n_post - 1) {
                 integrate_root(x, E);
             } else {
-                st4(a.post + (size_t)(dest - a.N) * a.stride + ((size_t)k * a.P_pad + p) * 4, x);
+                st4(post_ptr(dest), x);
                 if (k == 0) a.pexp[(size_t)(dest - a.N) * a.P_pad + p] = E;
             }
+            prev = dest;
+            prev_x = x;
+            prev_e = E;
+            in1 = nx1;
+            in2 = nx2;
         }
     }
 
     if (MODE & kRootBuf) {
-        const V4<T> x =
-            ld4(a.post + (size_t)(a.root_buf - a.N) * a.stride + ((size_t)k * a.P_pad + p) * 4);
+        const V4<T> x = ld4(post_ptr(a.root_buf));
         integrate_root(x, a.pexp[(size_t)(a.root_buf - a.N) * a.P_pad + p]);
     }
 
@@ -210,15 +256,32 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
         const T wrk = T(as_const(a.cat_w)[k] * as_const(a.cat_r)[k]);
         const double cp = a.pw[p];
         const int wave_b = K > 1 ? 1 : 0;
+        ChildIn<T> in1{}, in2{}, nx1{}, nx2{};
+        V4<T> qin{}, qnx{};
+        int pq1 = -1, pq2 = -1;          // pre buffers the previous operation produced
+        V4<T> pr1{}, pr2{};              // and their values
+        auto fetch_op = [&](int jj, int f1, int f2, ChildIn<T>& c1i, ChildIn<T>& c2i, V4<T>& q) {
+            cptr<int32_t> o = as_const(a.pre_ops + (size_t)jj * kPreOpInts);
+            const int pp = o[0];
+            if (pp >= 0 && pp != f1 && pp != f2) q = ld4(pre_ptr(pp));
+            fetch(o[1], -1, c1i);
+            fetch(o[5], -1, c2i);
+        };
+        if (a.n_pre > 0) fetch_op(0, -1, -1, in1, in2, qin);
         for (int j = 0; j < a.n_pre; ++j) {
             cptr<int32_t> op = as_const(a.pre_ops + (size_t)j * kPreOpInts);
             const int pp = op[0];
             const int c1 = op[1], m1 = op[2], q1 = op[3], g1 = op[4];
             const int c2 = op[5], m2 = op[6], q2 = op[7], g2 = op[8];
-            const V4<T> qn = pp < 0 ? ld4(as_const(a.freq))
-                                    : ld4(a.pre + (size_t)pp * a.stride + ((size_t)k * a.P_pad + p) * 4);
-            const V4<T> ua = child_u(a, c1, m1, k, p);
-            const V4<T> ub = child_u(a, c2, m2, k, p);
+            int nxt_pp = -2;
+            if (j + 1 < a.n_pre) {
+                nxt_pp = as_const(a.pre_ops + (size_t)(j + 1) * kPreOpInts)[0];
+                fetch_op(j + 1, q1, q2, nx1, nx2, qnx);
+            }
+            const V4<T> qn = pp < 0 ? ld4(as_const(a.freq)) : (pp == pq1 ? pr1 : (pp == pq2 ? pr2 : qin));
+            int e_unused;
+            const V4<T> ua = resolve(c1, m1, in1, -1, prev_none<T>(), 0, e_unused);
+            const V4<T> ub = resolve(c2, m2, in2, -1, prev_none<T>(), 0, e_unused);
             const V4<T> va = mul(qn, ub);
             const V4<T> vb = mul(qn, ua);
             V4<T> qa{}, qb{};
@@ -271,10 +334,21 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             }
             ea = (ea == INT_MIN) ? 0 : ea;
             eb = (eb == INT_MIN) ? 0 : eb;
-            if (q1 >= 0)
-                st4(a.pre + (size_t)q1 * a.stride + ((size_t)k * a.P_pad + p) * 4, ldexp4(qa, -ea));
-            if (q2 >= 0)
-                st4(a.pre + (size_t)q2 * a.stride + ((size_t)k * a.P_pad + p) * 4, ldexp4(qb, -eb));
+            // in whole-tree evaluation a pre-order partial is read once, by its own node's
+            // operation: when that is the next operation it is forwarded and never stored
+            if (q1 >= 0) {
+                pr1 = ldexp4(qa, -ea);
+                if (!(a.tree && nxt_pp == q1)) st4(pre_ptr(q1), pr1);
+            }
+            if (q2 >= 0) {
+                pr2 = ldexp4(qb, -eb);
+                if (!(a.tree && nxt_pp == q2)) st4(pre_ptr(q2), pr2);
+            }
+            pq1 = q1;
+            pq2 = q2;
+            in1 = nx1;
+            in2 = nx2;
+            qin = qnx;
         }
     }
 }
@@ -323,6 +397,7 @@ WalkDev<T> make_desc(const Instance& I, const WalkArgs& w) {
     a.K = I.d.n_categories;
     a.S = I.d.n_states;
     a.rescale_pre = I.d.scaling != HP_SCALE_NONE;
+    a.tree = w.tree ? 1 : 0;
     return a;
 }
 
