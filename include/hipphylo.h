@@ -22,7 +22,8 @@
  *    are addressed as n_tips..n_tips+n_partials-1 (so a tree's internal node v
  *    can use post buffer v); pre-order partial buffers are 0..n_partials-1.
  *  - Partials are stored on the device as [category][pattern][state] with the
- *    pattern count padded to a multiple of 64 and the state count padded
+ *    pattern count padded (to a multiple of 128 for n_states <= 4, else of 64)
+ *    and the state count padded
  *    (hp_query HP_Q_STATE_PAD, HP_Q_PATTERN_PAD); padding patterns carry weight
  *    0 and an unknown state at every tip, so they contribute exactly nothing.
  *  - Device memory: the library never allocates device memory.  The caller
@@ -137,6 +138,11 @@ int hp_last_error(const hp_instance* inst, char* buf, size_t len);
 #define HP_Q_ELEMENT_BYTES  3
 #define HP_Q_BLOCKS         4  /* pattern tiles (workgroups) one traversal launches   */
 #define HP_Q_RUNTIME_VERSION 5 /* hipRuntimeGetVersion() of the runtime in use        */
+#define HP_Q_TILE           6  /* patterns per traversal workgroup.  For n_states <= 4 it is
+                                  64 or 128, chosen by hp_create from the device's occupancy
+                                  so that the launch fills whole rounds of resident
+                                  workgroups (environment HIPPHYLO_SMALL_PPL=1|2 forces
+                                  64 or 128 patterns per workgroup); 16 otherwise        */
 int hp_query(const hp_instance* inst, int what, int64_t* out);
 
 /* ---------------------------------------------------------------- data */
@@ -229,7 +235,7 @@ int hp_gradients_device(hp_instance* inst, double* d_grad);
 /* ---------------------------------------------------------------- batched evaluation
  * Whole-tree evaluations of up to HP_MAX_BATCH instances in one launch per kernel (matrix
  * assembly, traversal, reduction), for serving many clients.  The instances must share
- * device, precision, state padding and category count, must each have had hp_set_tree and
+ * device, precision, state padding, category count and tile (HP_Q_TILE), must each have had hp_set_tree and
  * model slot 0 set, and may each appear only once; their trees, pattern counts and models
  * may differ.  d_t[i] (2N_i-2 FP64) and d_out[i] (1 + 2N_i-2 FP64 with gradients, else 1)
  * are device pointers.  Work is enqueued on hip_stream (not on the instances' streams) and

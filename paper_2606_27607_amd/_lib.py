@@ -35,6 +35,7 @@ HP_Q_PATTERN_PAD = 2
 HP_Q_ELEMENT_BYTES = 3
 HP_Q_BLOCKS = 4
 HP_Q_RUNTIME_VERSION = 5
+HP_Q_TILE = 6
 
 
 class hp_desc(ctypes.Structure):

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -94,14 +95,16 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     int S_pad;
     if (S <= 4) S_pad = 4;                 // vector-ALU path
     else S_pad = S <= 32 ? 32 : 64;        // matrix-core path: MFMA tiles of 16 states
-    const int P_pad = (d.n_patterns + kWave - 1) / kWave * kWave;
+    // the 4-state path pads to its largest tile so that the tile can be chosen at creation
+    const int pad = S_pad == 4 ? kWave * kMaxSmallPpl : kWave;
+    const int P_pad = (d.n_patterns + pad - 1) / pad * pad;
     const int elem = d.precision == HP_PREC_F64 ? 8 : d.precision == HP_PREC_F32 ? 4 : 2;
     const int celem = d.precision == HP_PREC_F64 ? 8 : 4;  // matrices / Q / freqs: FP64 or FP32
     const size_t np = (size_t)d.n_partials, nm = (size_t)d.n_matrices, ne = (size_t)d.n_eigen;
     Layout l{};
     const bool mfma = S_pad > 4;
-    l.tile = mfma ? kMfmaTile : kWave;
-    l.n_blocks = P_pad / l.tile;
+    l.tile = mfma ? kMfmaTile : kWave;  // 4-state path: the smallest tile, sizing the partials
+    l.n_blocks = (d.n_patterns + l.tile - 1) / l.tile;
     if (mfma && l.n_blocks > kMaxMfmaBlocks) l.n_blocks = kMaxMfmaBlocks;
     const int n_blocks = l.n_blocks;
     l.post_stride = (size_t)K * P_pad * S_pad;
@@ -248,6 +251,62 @@ int check_mat(Instance* I, int m) {
 
 }  // namespace
 
+namespace {
+
+// Patterns per lane of the 4-state traversal.  Every workgroup walks the whole tree, so a
+// launch is a few rounds of resident workgroups and a round costs nearly a full walk even
+// when it is almost empty (the walk is latency-bound).  Estimate each choice's time as
+// rounds (the last one counted as at least half) times the pattern slots of a round times
+// the relative cost of a pattern slot (two patterns per lane measured about 1.2x slower
+// per pattern than one, at equal residency), and keep the cheaper; ties go to one pattern
+// per lane.  HIPPHYLO_SMALL_PPL=1|2 overrides the choice (tuning).
+void choose_small_tile(Instance* I) {
+    const int P = I->d.n_patterns;
+    int best = 1;
+    if (const char* env = std::getenv("HIPPHYLO_SMALL_PPL")) {
+        const int v = std::atoi(env);
+        if (v >= 1 && v <= hp::kMaxSmallPpl) best = v;
+    } else {
+        int n_cu = 0;
+        if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, I->d.device) != hipSuccess)
+            n_cu = 0;
+        double best_cost = 0.0;
+        for (int ppl = 1; ppl <= hp::kMaxSmallPpl; ++ppl) {
+            const int per_cu = hp::small_blocks_per_cu(*I, ppl);
+            if (per_cu <= 0 || n_cu <= 0) continue;
+            const long cap = (long)per_cu * n_cu;
+            const long nb = (P + hp::kWave * ppl - 1) / (hp::kWave * ppl);
+            const double rem = double(nb % cap) / double(cap);
+            const double rounds = double(nb / cap) + (rem > 0.0 ? std::max(0.5, rem) : 0.0);
+            const double cost = rounds * double(cap) * ppl * (ppl == 1 ? 1.0 : 1.2);
+            if (ppl == 1 || cost < best_cost) {
+                best = ppl;
+                best_cost = cost;
+            }
+        }
+    }
+    I->L.tile = hp::kWave * best;
+    I->L.n_blocks = I->n_blocks = (P + I->L.tile - 1) / I->L.tile;
+}
+
+// Workgroups of a matrix-core launch.  Each walks groups of pattern tiles in a grid-stride
+// loop, so launching no more workgroups than the device holds at once keeps the whole grid
+// resident and balances it to within one group per workgroup; never more than there are
+// groups (an idle workgroup still zeroes its reduction column).
+void choose_mfma_blocks(Instance* I) {
+    int ct = 1, per_cu = 0, n_cu = 0;
+    hp::tree_shape_mfma(*I, &ct, &per_cu);
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, I->d.device) != hipSuccess)
+        n_cu = 0;
+    const long groups = (long)(I->P_pad / hp::kMfmaTile) / ct;
+    long nb = groups;
+    if (per_cu > 0 && n_cu > 0) nb = std::min(nb, (long)per_cu * n_cu);
+    nb = std::max(1L, std::min(nb, (long)I->L.n_blocks));
+    I->L.n_blocks = I->n_blocks = (int)nb;
+}
+
+}  // namespace
+
 // ===================================================================== C ABI
 
 extern "C" {
@@ -280,6 +339,8 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
         return fail(nullptr, HP_ERR_WORKSPACE, "workspace smaller than hp_workspace_bytes");
     }
     I->n_blocks = I->L.n_blocks;
+    if (I->S_pad == 4) choose_small_tile(I);
+    else choose_mfma_blocks(I);
     I->ws = static_cast<uint8_t*>(dev_workspace);
     I->ws_bytes = workspace_bytes;
     I->stream = static_cast<hipStream_t>(hip_stream);
@@ -357,6 +418,7 @@ int hp_query(const hp_instance* inst, int what, int64_t* out) {
         case HP_Q_PATTERN_PAD: *out = I->P_pad; return HP_OK;
         case HP_Q_ELEMENT_BYTES: *out = I->elem; return HP_OK;
         case HP_Q_BLOCKS: *out = I->n_blocks; return HP_OK;
+        case HP_Q_TILE: *out = I->L.tile; return HP_OK;
         case HP_Q_RUNTIME_VERSION: {
             int v = 0;
             if (hipRuntimeGetVersion(&v) != hipSuccess) return HP_ERR_DEVICE;
@@ -826,9 +888,9 @@ int hp_batch_evaluate_device(hp_instance* const* insts, const double* const* d_t
         for (int j = 0; j < i; ++j)
             if (insts[j] == insts[i]) return fail(nullptr, HP_ERR_ARG, "an instance appears twice in one batch");
         if (I->d.device != first->d.device || I->d.precision != first->d.precision ||
-            I->S_pad != first->S_pad || I->d.n_categories != first->d.n_categories)
+            I->S_pad != first->S_pad || I->d.n_categories != first->d.n_categories || I->L.tile != first->L.tile)
             return fail(nullptr, HP_ERR_UNSUPPORTED,
-                        "batched instances must share device, precision, state padding and categories");
+                        "batched instances must share device, precision, state padding, categories and tile");
         if (!I->tree_set || !I->eigen_set[0] || !I->freq_set[0])
             return fail(nullptr, HP_ERR_STATE, "a batched instance lacks its tree or model");
         const int N = I->d.n_tips;

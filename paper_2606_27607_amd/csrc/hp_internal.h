@@ -19,6 +19,7 @@ constexpr int kPostOpInts = 6;     // hp_post_op
 constexpr int kPreOpInts = 9;      // hp_pre_op
 constexpr int kMfmaTile = 16;      // patterns per matrix-core tile
 constexpr int kMaxMfmaBlocks = 2048;
+constexpr int kMaxSmallPpl = 2;    // patterns per lane of the 4-state kernels: 1 or 2
 
 // Device status bits (hp_status).
 constexpr int kStatusValue = 1;    // invalid branch length seen by the matrix kernel
@@ -45,7 +46,7 @@ struct Layout {
     size_t tip_stride;    // elements per tip-table slot (K * (S+1) * S_pad)
     size_t eig_stride;    // doubles per eigen slot (2 S^2 + S)
     int max_out;          // output slots per reduction row (1 + max gradients)
-    int tile;             // patterns per traversal tile (64 vector path, 16 matrix-core path)
+    int tile;             // patterns per traversal tile (64 or 128 vector path, 16 matrix-core path)
     int n_blocks;         // workgroups of one traversal launch = columns of a reduction row
 };
 
@@ -188,6 +189,10 @@ hipError_t launch_walk(const Instance& I, const WalkArgs& a);
 size_t build_tree_desc(const Instance& I, int want_grad, void* host_buf);
 PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx);
 hipError_t launch_batch(const Instance& first, const BatchArgs& b, int want_grad);
+// Workgroups of the 4-state whole-tree kernel one CU holds with `ppl` patterns per lane.
+int small_blocks_per_cu(const Instance& I, int ppl);
+// Pattern tiles per wave of the matrix-core whole-tree kernel and its workgroups per CU.
+void tree_shape_mfma(const Instance& I, int* tiles_per_group, int* blocks_per_cu);
 // out[i] = sum over workgroups of reduction slot first + i, for i < n_out.
 hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first = 0);
 hipError_t launch_fill_i32(const Instance& I, int32_t* p, int32_t v, size_t n);

@@ -124,27 +124,29 @@ struct WalkDev {
     int tree;               // whole-tree lists: pre-order partials are read once (see below)
 };
 
-// What one child edge of an operation needs for the lane: its tip state, or its partial
-// and cumulative exponent.
-template <typename T>
+// What one child edge of an operation needs for each pattern slot of the lane: its tip
+// state, or its partial and cumulative exponent.
+template <typename T, int PPL>
 struct ChildIn {
-    V4<T> v;
-    int e;
-    int s;
+    V4<T> v[PPL];
+    int e[PPL];
+    int s[PPL];
 };
 
-template <typename T>
-__device__ __forceinline__ V4<T> prev_none() {
-    return V4<T>{};
-}
-
-template <typename T, int KMAX, int MODE>
+// One workgroup = one tile of kWave * PPL patterns; lane l of every wave handles the
+// patterns l, l + kWave, ... of the tile (slot j = pattern l + j * kWave), so each load or
+// store of a wave is still PPL contiguous runs.  More patterns per lane means fewer,
+// longer-lived waves with more independent memory operations each: the host picks PPL so
+// that the whole grid is resident at once where it can (a second, nearly empty round of
+// workgroups costs almost a full latency-bound tree walk).
+template <typename T, int KMAX, int PPL, int MODE>
 __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int block) {
-    __shared__ int sh_e[2][2][KMAX][kWave];
-    __shared__ T sh_v[2][3][KMAX][kWave];
+    constexpr int TW = kWave * PPL;
+    __shared__ int sh_e[2][2][KMAX][TW];
+    __shared__ T sh_v[2][3][KMAX][TW];
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    const int p = block * kWave + lane;
+    const int p0 = block * TW + lane;
     const int K = a.K;
     int sb = 0;  // exchange counter: consecutive LDS exchanges alternate buffers
 
@@ -154,57 +156,88 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
         __syncthreads();
     }
 
-    auto integrate_root = [&](const V4<T>& x, int E) {
+    auto integrate_root = [&](const V4<T> (&x)[PPL], const int (&E)[PPL]) {
         const int s = (sb++) & 1;
-        sh_v[s][0][k][lane] = T(as_const(a.cat_w)[k]) * dot(ld4(as_const(a.freq)), x);
+        const T wk = T(as_const(a.cat_w)[k]);
+        const V4<T> fr = ld4(as_const(a.freq));
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) sh_v[s][0][k][lane + j * kWave] = wk * dot(fr, x[j]);
         __syncthreads();
         if (k == 0) {
-            double L = 0.0;
-            for (int kk = 0; kk < K; ++kk) L += double(sh_v[s][0][kk][lane]);
-            double l = log(L) + double(E) * 0.69314718055994530942;
-            if (!(L > 0.0) || !isfinite(l)) {
-                atomicOr(a.status, kStatusNumeric);
-                l = -INFINITY;
+            double tot = 0.0;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                const int p = p0 + j * kWave;
+                double L = 0.0;
+                for (int kk = 0; kk < K; ++kk) L += double(sh_v[s][0][kk][lane + j * kWave]);
+                double l = log(L) + double(E[j]) * 0.69314718055994530942;
+                if (!(L > 0.0) || !isfinite(l)) {
+                    atomicOr(a.status, kStatusNumeric);
+                    l = -INFINITY;
+                }
+                if (a.site) a.site[p] = l;
+                const double w = a.pw[p];
+                tot += w == 0.0 ? 0.0 : w * l;
             }
-            if (a.site) a.site[p] = l;
-            const double w = a.pw[p];
-            double tot = wave_sum(w == 0.0 ? 0.0 : w * l);
+            tot = wave_sum(tot);
             if (lane == 0) a.h.partials[block] = tot;
         }
     };
 
-    // Each operation's inputs that do not depend on the previous operation are loaded one
-    // operation ahead (prefetch), and an input that the previous operation produced is taken
-    // from registers (forwarding) instead of a store-load round trip.  Both keep the exact
-    // values memory would have returned, so results do not change.
-    auto post_ptr = [&](int c) { return a.post + (size_t)(c - a.N) * a.stride + ((size_t)k * a.P_pad + p) * 4; };
-    auto pre_ptr = [&](int q) { return a.pre + (size_t)q * a.stride + ((size_t)k * a.P_pad + p) * 4; };
+    // With one pattern per lane, each operation's inputs that do not depend on the previous
+    // operation are loaded one operation ahead (prefetch); with two, the second pattern
+    // already doubles the independent loads in flight and the registers a prefetch would
+    // hold cost occupancy instead.  An input that the previous operation produced is always
+    // taken from registers (forwarding) instead of a store-load round trip.  Both keep the
+    // exact values memory would have returned, so results do not change.
+    constexpr bool kPf = PPL == 1;
+    auto post_ptr = [&](int c, int j) {
+        return a.post + (size_t)(c - a.N) * a.stride + ((size_t)k * a.P_pad + p0 + j * kWave) * 4;
+    };
+    auto pre_ptr = [&](int q, int j) {
+        return a.pre + (size_t)q * a.stride + ((size_t)k * a.P_pad + p0 + j * kWave) * 4;
+    };
+    auto exp_ptr = [&](int c, int j) { return a.pexp + (size_t)(c - a.N) * a.P_pad + p0 + j * kWave; };
     // load what a child edge needs unless the child is `fwd` (produced by the operation before)
-    auto fetch = [&](int c, int fwd, ChildIn<T>& ci) {
+    auto fetch = [&](int c, int fwd, ChildIn<T, PPL>& ci) {
         if (c < a.N) {
-            ci.s = a.tips[(size_t)c * a.P_pad + p];
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) ci.s[j] = a.tips[(size_t)c * a.P_pad + p0 + j * kWave];
         } else if (c != fwd) {
-            ci.v = ld4(post_ptr(c));
-            ci.e = a.pexp[(size_t)(c - a.N) * a.P_pad + p];
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                ci.v[j] = ld4(post_ptr(c, j));
+                ci.e[j] = *exp_ptr(c, j);
+            }
         }
     };
     // u = P_m x for the child (x: tip column, forwarded or loaded partial) and its exponent
-    auto resolve = [&](int c, int m, const ChildIn<T>& ci, int fwd, const V4<T>& fx, int fe, int& e) {
+    auto resolve = [&](int c, int m, const ChildIn<T, PPL>& ci, int fwd, const V4<T> (&fx)[PPL],
+                       const int (&fe)[PPL], V4<T> (&u)[PPL], int (&e)[PPL]) {
         if (c < a.N) {
-            e = 0;
-            const int st = ci.s > a.S ? a.S : ci.s;
-            return ld4(a.tiptab + ((size_t)(m * K + k) * (a.S + 1) + st) * 4);
+            const T* col = a.tiptab + (size_t)(m * K + k) * (a.S + 1) * 4;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                e[j] = 0;
+                u[j] = ld4(col + (ci.s[j] > a.S ? a.S : ci.s[j]) * 4);
+            }
+            return;
         }
         const bool f = c == fwd;
-        e = f ? fe : ci.e;
-        return matvec(as_const(a.mats + (size_t)(m * K + k) * 16), f ? fx : ci.v);
+        const cptr<T> Pm = as_const(a.mats + (size_t)(m * K + k) * 16);
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            e[j] = f ? fe[j] : ci.e[j];
+            u[j] = matvec(Pm, f ? fx[j] : ci.v[j]);
+        }
     };
 
     if (MODE & kPost) {
-        ChildIn<T> in1{}, in2{}, nx1{}, nx2{};
-        int prev = -1, prev_e = 0;
-        V4<T> prev_x{};
-        if (a.n_post > 0) {
+        ChildIn<T, PPL> in1{}, in2{}, nx1{}, nx2{};
+        int prev = -1;
+        V4<T> prev_x[PPL] = {};
+        int prev_e[PPL] = {};
+        if (kPf && a.n_post > 0) {
             cptr<int32_t> op0 = as_const(a.post_ops);
             fetch(op0[1], -1, in1);
             fetch(op0[3], -1, in2);
@@ -212,109 +245,166 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
         for (int i = 0; i < a.n_post; ++i) {
             cptr<int32_t> op = as_const(a.post_ops + (size_t)i * kPostOpInts);
             const int dest = op[0], c1 = op[1], m1 = op[2], c2 = op[3], m2 = op[4], resc = op[5];
-            if (i + 1 < a.n_post) {
+            if (!kPf) {
+                fetch(c1, prev, in1);
+                fetch(c2, prev, in2);
+            } else if (i + 1 < a.n_post) {
                 cptr<int32_t> on = as_const(a.post_ops + (size_t)(i + 1) * kPostOpInts);
                 fetch(on[1], dest, nx1);
                 fetch(on[3], dest, nx2);
             }
-            int e1, e2;
-            const V4<T> u1 = resolve(c1, m1, in1, prev, prev_x, prev_e, e1);
-            const V4<T> u2 = resolve(c2, m2, in2, prev, prev_x, prev_e, e2);
-            V4<T> x = mul(u1, u2);
-            int E = e1 + e2;
+            V4<T> u1[PPL], u2[PPL], x[PPL];
+            int e1[PPL], e2[PPL], E[PPL];
+            resolve(c1, m1, in1, prev, prev_x, prev_e, u1, e1);
+            resolve(c2, m2, in2, prev, prev_x, prev_e, u2, e2);
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                x[j] = mul(u1[j], u2[j]);
+                E[j] = e1[j] + e2[j];
+            }
             if (resc) {
                 const int s = (sb++) & 1;
-                sh_e[s][0][k][lane] = scale_exp(max4(x));
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) sh_e[s][0][k][lane + j * kWave] = scale_exp(max4(x[j]));
                 __syncthreads();
-                int em = sh_e[s][0][0][lane];
-                for (int kk = 1; kk < K; ++kk) em = max(em, sh_e[s][0][kk][lane]);
-                em = (em == INT_MIN) ? 0 : em;
-                x = ldexp4(x, -em);
-                E += em;
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    int em = sh_e[s][0][0][lane + j * kWave];
+                    for (int kk = 1; kk < K; ++kk) em = max(em, sh_e[s][0][kk][lane + j * kWave]);
+                    em = (em == INT_MIN) ? 0 : em;
+                    x[j] = ldexp4(x[j], -em);
+                    E[j] += em;
+                }
             }
             if ((MODE & kRootFused) && i == a.n_post - 1) {
                 integrate_root(x, E);
             } else {
-                st4(post_ptr(dest), x);
-                if (k == 0) a.pexp[(size_t)(dest - a.N) * a.P_pad + p] = E;
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    st4(post_ptr(dest, j), x[j]);
+                    if (k == 0) *exp_ptr(dest, j) = E[j];
+                }
             }
             prev = dest;
-            prev_x = x;
-            prev_e = E;
-            in1 = nx1;
-            in2 = nx2;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                prev_x[j] = x[j];
+                prev_e[j] = E[j];
+            }
+            if (kPf) {
+                in1 = nx1;
+                in2 = nx2;
+            }
         }
     }
 
     if (MODE & kRootBuf) {
-        const V4<T> x = ld4(post_ptr(a.root_buf));
-        integrate_root(x, a.pexp[(size_t)(a.root_buf - a.N) * a.P_pad + p]);
+        V4<T> x[PPL];
+        int E[PPL];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            x[j] = ld4(post_ptr(a.root_buf, j));
+            E[j] = *exp_ptr(a.root_buf, j);
+        }
+        integrate_root(x, E);
     }
 
     if (MODE & kPre) {
         const T wk = T(as_const(a.cat_w)[k]);
         const T wrk = T(as_const(a.cat_w)[k] * as_const(a.cat_r)[k]);
-        const double cp = a.pw[p];
+        double cp[PPL];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) cp[j] = a.pw[p0 + j * kWave];
         const int wave_b = K > 1 ? 1 : 0;
-        ChildIn<T> in1{}, in2{}, nx1{}, nx2{};
-        V4<T> qin{}, qnx{};
-        int pq1 = -1, pq2 = -1;          // pre buffers the previous operation produced
-        V4<T> pr1{}, pr2{};              // and their values
-        auto fetch_op = [&](int jj, int f1, int f2, ChildIn<T>& c1i, ChildIn<T>& c2i, V4<T>& q) {
+        const V4<T> none[PPL] = {};
+        const int none_e[PPL] = {};
+        ChildIn<T, PPL> in1{}, in2{}, nx1{}, nx2{};
+        V4<T> qin[PPL] = {}, qnx[PPL] = {};
+        int pq1 = -1, pq2 = -1;                  // pre buffers the previous operation produced
+        V4<T> pr1[PPL] = {}, pr2[PPL] = {};      // and their values
+        auto fetch_op = [&](int jj, int f1, int f2, ChildIn<T, PPL>& c1i, ChildIn<T, PPL>& c2i,
+                            V4<T> (&q)[PPL]) {
             cptr<int32_t> o = as_const(a.pre_ops + (size_t)jj * kPreOpInts);
             const int pp = o[0];
-            if (pp >= 0 && pp != f1 && pp != f2) q = ld4(pre_ptr(pp));
+            if (pp >= 0 && pp != f1 && pp != f2) {
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) q[j] = ld4(pre_ptr(pp, j));
+            }
             fetch(o[1], -1, c1i);
             fetch(o[5], -1, c2i);
         };
-        if (a.n_pre > 0) fetch_op(0, -1, -1, in1, in2, qin);
-        for (int j = 0; j < a.n_pre; ++j) {
-            cptr<int32_t> op = as_const(a.pre_ops + (size_t)j * kPreOpInts);
+        if (kPf && a.n_pre > 0) fetch_op(0, -1, -1, in1, in2, qin);
+        for (int i = 0; i < a.n_pre; ++i) {
+            cptr<int32_t> op = as_const(a.pre_ops + (size_t)i * kPreOpInts);
             const int pp = op[0];
             const int c1 = op[1], m1 = op[2], q1 = op[3], g1 = op[4];
             const int c2 = op[5], m2 = op[6], q2 = op[7], g2 = op[8];
             int nxt_pp = -2;
-            if (j + 1 < a.n_pre) {
-                nxt_pp = as_const(a.pre_ops + (size_t)(j + 1) * kPreOpInts)[0];
-                fetch_op(j + 1, q1, q2, nx1, nx2, qnx);
+            if (!kPf) fetch_op(i, pq1, pq2, in1, in2, qin);
+            if (i + 1 < a.n_pre) {
+                nxt_pp = as_const(a.pre_ops + (size_t)(i + 1) * kPreOpInts)[0];
+                if (kPf) fetch_op(i + 1, q1, q2, nx1, nx2, qnx);
             }
-            const V4<T> qn = pp < 0 ? ld4(as_const(a.freq)) : (pp == pq1 ? pr1 : (pp == pq2 ? pr2 : qin));
-            int e_unused;
-            const V4<T> ua = resolve(c1, m1, in1, -1, prev_none<T>(), 0, e_unused);
-            const V4<T> ub = resolve(c2, m2, in2, -1, prev_none<T>(), 0, e_unused);
-            const V4<T> va = mul(qn, ub);
-            const V4<T> vb = mul(qn, ua);
-            V4<T> qa{}, qb{};
-            int ea = INT_MIN, eb = INT_MIN;
+            V4<T> qn[PPL], ua[PPL], ub[PPL], va[PPL], vb[PPL], qa[PPL] = {}, qb[PPL] = {};
+            int e_unused[PPL], ea[PPL], eb[PPL];
+            const V4<T> fr = ld4(as_const(a.freq));
+#pragma unroll
+            for (int j = 0; j < PPL; ++j)
+                qn[j] = pp < 0 ? fr : (pp == pq1 ? pr1[j] : (pp == pq2 ? pr2[j] : qin[j]));
+            resolve(c1, m1, in1, -1, none, none_e, ua, e_unused);
+            resolve(c2, m2, in2, -1, none, none_e, ub, e_unused);
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                va[j] = mul(qn[j], ub[j]);
+                vb[j] = mul(qn[j], ua[j]);
+                ea[j] = INT_MIN;
+                eb[j] = INT_MIN;
+            }
             if (q1 >= 0) {
-                qa = mattvec(as_const(a.mats + (size_t)(m1 * K + k) * 16), va);
-                if (a.rescale_pre) ea = scale_exp(max4(qa));
+                const cptr<T> Pm = as_const(a.mats + (size_t)(m1 * K + k) * 16);
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    qa[j] = mattvec(Pm, va[j]);
+                    if (a.rescale_pre) ea[j] = scale_exp(max4(qa[j]));
+                }
             }
             if (q2 >= 0) {
-                qb = mattvec(as_const(a.mats + (size_t)(m2 * K + k) * 16), vb);
-                if (a.rescale_pre) eb = scale_exp(max4(qb));
+                const cptr<T> Pm = as_const(a.mats + (size_t)(m2 * K + k) * 16);
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    qb[j] = mattvec(Pm, vb[j]);
+                    if (a.rescale_pre) eb[j] = scale_exp(max4(qb[j]));
+                }
             }
             const bool grad = (MODE & kGrad) && (g1 >= 0 || g2 >= 0);
             const bool resc = a.rescale_pre && (q1 >= 0 || q2 >= 0);
             if (grad || resc) {
                 const int s = (sb++) & 1;
-                if (resc) {
-                    sh_e[s][0][k][lane] = ea;
-                    sh_e[s][1][k][lane] = eb;
-                }
-                if (grad) {
-                    cptr<T> Qp = as_const(a.Q);
-                    sh_v[s][0][k][lane] = wk * dot(va, ua);  // = w_k pre_c^T post_c, same for both
-                    sh_v[s][1][k][lane] = g1 >= 0 ? wrk * dot(va, matvec(Qp, ua)) : T(0);
-                    sh_v[s][2][k][lane] = g2 >= 0 ? wrk * dot(vb, matvec(Qp, ub)) : T(0);
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    const int l = lane + j * kWave;
+                    if (resc) {
+                        sh_e[s][0][k][l] = ea[j];
+                        sh_e[s][1][k][l] = eb[j];
+                    }
+                    if (grad) {
+                        const cptr<T> Qp = as_const(a.Q);
+                        sh_v[s][0][k][l] = wk * dot(va[j], ua[j]);  // = w_k pre_c^T post_c, both sides
+                        sh_v[s][1][k][l] = g1 >= 0 ? wrk * dot(va[j], matvec(Qp, ua[j])) : T(0);
+                        sh_v[s][2][k][l] = g2 >= 0 ? wrk * dot(vb[j], matvec(Qp, ub[j])) : T(0);
+                    }
                 }
                 __syncthreads();
                 if (resc) {
-                    ea = sh_e[s][0][0][lane];
-                    eb = sh_e[s][1][0][lane];
-                    for (int kk = 1; kk < K; ++kk) {
-                        ea = max(ea, sh_e[s][0][kk][lane]);
-                        eb = max(eb, sh_e[s][1][kk][lane]);
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        const int l = lane + j * kWave;
+                        ea[j] = sh_e[s][0][0][l];
+                        eb[j] = sh_e[s][1][0][l];
+                        for (int kk = 1; kk < K; ++kk) {
+                            ea[j] = max(ea[j], sh_e[s][0][kk][l]);
+                            eb[j] = max(eb[j], sh_e[s][1][kk][l]);
+                        }
                     }
                 }
                 if (grad) {
@@ -322,48 +412,66 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                     for (int side = 0; side < 2; ++side) {
                         const int g = side ? g2 : g1;
                         if (g < 0 || k != (side ? wave_b : 0)) continue;
-                        double den = 0.0, num = 0.0;
-                        for (int kk = 0; kk < K; ++kk) {
-                            den += double(sh_v[s][0][kk][lane]);
-                            num += double(sh_v[s][1 + side][kk][lane]);
+                        double tot = 0.0;
+#pragma unroll
+                        for (int j = 0; j < PPL; ++j) {
+                            const int l = lane + j * kWave;
+                            double den = 0.0, num = 0.0;
+                            for (int kk = 0; kk < K; ++kk) {
+                                den += double(sh_v[s][0][kk][l]);
+                                num += double(sh_v[s][1 + side][kk][l]);
+                            }
+                            tot += cp[j] == 0.0 ? 0.0 : cp[j] * (num / den);
                         }
-                        const double tot = wave_sum(cp == 0.0 ? 0.0 : cp * (num / den));
+                        tot = wave_sum(tot);
                         if (lane == 0) a.h.partials[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
                     }
                 }
             }
-            ea = (ea == INT_MIN) ? 0 : ea;
-            eb = (eb == INT_MIN) ? 0 : eb;
             // in whole-tree evaluation a pre-order partial is read once, by its own node's
             // operation: when that is the next operation it is forwarded and never stored
-            if (q1 >= 0) {
-                pr1 = ldexp4(qa, -ea);
-                if (!(a.tree && nxt_pp == q1)) st4(pre_ptr(q1), pr1);
-            }
-            if (q2 >= 0) {
-                pr2 = ldexp4(qb, -eb);
-                if (!(a.tree && nxt_pp == q2)) st4(pre_ptr(q2), pr2);
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                if (q1 >= 0) {
+                    pr1[j] = ldexp4(qa[j], ea[j] == INT_MIN ? 0 : -ea[j]);
+                    if (!(a.tree && nxt_pp == q1)) st4(pre_ptr(q1, j), pr1[j]);
+                }
+                if (q2 >= 0) {
+                    pr2[j] = ldexp4(qb[j], eb[j] == INT_MIN ? 0 : -eb[j]);
+                    if (!(a.tree && nxt_pp == q2)) st4(pre_ptr(q2, j), pr2[j]);
+                }
+                if (kPf) qin[j] = qnx[j];
             }
             pq1 = q1;
             pq2 = q2;
-            in1 = nx1;
-            in2 = nx2;
-            qin = qnx;
+            if (kPf) {
+                in1 = nx1;
+                in2 = nx2;
+            }
         }
     }
 }
 
-template <typename T, int KMAX, int MODE>
-__global__ void __launch_bounds__(KMAX * kWave) walk_small(const WalkDev<T> a) {
-    walk_small_body<T, KMAX, MODE>(a, blockIdx.x);
+// Waves per SIMD the FP32 kernels are register-limited to: 7 with one pattern per lane
+// (72 VGPRs; the compiler's own choice of 79 allows only 6, and a grid that just misses
+// full residency pays a second, nearly empty round), 4 with two (128 VGPRs).  FP64 keeps
+// the compiler's choice: fewer registers would spill.
+template <typename T, int PPL>
+constexpr int kSmallWavesPerEu = sizeof(T) == 4 ? (PPL == 1 ? 7 : 4) : 1;
+
+template <typename T, int KMAX, int PPL, int MODE>
+__global__ void __launch_bounds__(KMAX * kWave) __attribute__((amdgpu_waves_per_eu(kSmallWavesPerEu<T, PPL>)))
+walk_small(const WalkDev<T> a) {
+    walk_small_body<T, KMAX, PPL, MODE>(a, blockIdx.x);
 }
 
 // One launch over the tiles of several instances: block -> (instance, local block).
-template <typename T, int KMAX, int MODE>
-__global__ void __launch_bounds__(KMAX * kWave) walk_small_batched(const BatchArgs b) {
+template <typename T, int KMAX, int PPL, int MODE>
+__global__ void __launch_bounds__(KMAX * kWave) __attribute__((amdgpu_waves_per_eu(kSmallWavesPerEu<T, PPL>)))
+walk_small_batched(const BatchArgs b) {
     const int i = batch_find(b.walk_off, b.n, blockIdx.x);
     const WalkDev<T> a = load_desc<WalkDev<T>>(b.walk[i]);
-    walk_small_body<T, KMAX, MODE>(a, blockIdx.x - b.walk_off[i]);
+    walk_small_body<T, KMAX, PPL, MODE>(a, blockIdx.x - b.walk_off[i]);
 }
 
 template <typename T>
@@ -401,11 +509,11 @@ WalkDev<T> make_desc(const Instance& I, const WalkArgs& w) {
     return a;
 }
 
-template <typename T, int KMAX>
+template <typename T, int KMAX, int PPL>
 hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
     const WalkDev<T> a = make_desc<T>(I, w);
     dim3 grid(I.n_blocks), block(kWave * I.d.n_categories);
-#define HP_LAUNCH(M) hipLaunchKernelGGL((walk_small<T, KMAX, M>), grid, block, 0, I.stream, a)
+#define HP_LAUNCH(M) hipLaunchKernelGGL((walk_small<T, KMAX, PPL, M>), grid, block, 0, I.stream, a)
     switch (w.mode) {
         case kPost: HP_LAUNCH(kPost); break;
         case kPost | kRootFused: HP_LAUNCH(kPost | kRootFused); break;
@@ -419,19 +527,66 @@ hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
     return hipGetLastError();
 }
 
-template <typename T, int KMAX>
+template <typename T, int KMAX, int PPL>
 hipError_t dispatch_batch(const Instance& I, const BatchArgs& b, int want_grad) {
     dim3 grid(b.walk_off[b.n]), block(kWave * I.d.n_categories);
     if (want_grad)
-        hipLaunchKernelGGL((walk_small_batched<T, KMAX, kPost | kRootFused | kPre | kGrad>), grid, block, 0,
-                           I.stream, b);
+        hipLaunchKernelGGL((walk_small_batched<T, KMAX, PPL, kPost | kRootFused | kPre | kGrad>), grid, block,
+                           0, I.stream, b);
     else
-        hipLaunchKernelGGL((walk_small_batched<T, KMAX, kPost | kRootFused>), grid, block, 0, I.stream, b);
+        hipLaunchKernelGGL((walk_small_batched<T, KMAX, PPL, kPost | kRootFused>), grid, block, 0, I.stream, b);
     return hipGetLastError();
 }
 
+// Select the instantiation for (precision, category bound, patterns per lane) and call
+// f.template run<T, KMAX, PPL>() on it.
+template <typename F>
+hipError_t with_variant(const Instance& I, int ppl, const F& f) {
+    const bool f64 = I.d.precision == HP_PREC_F64;
+    const bool k4 = I.d.n_categories <= 4;
+    if (ppl == 2) {
+        if (f64) return k4 ? f.template run<double, 4, 2>() : f.template run<double, 8, 2>();
+        return k4 ? f.template run<float, 4, 2>() : f.template run<float, 8, 2>();
+    }
+    if (f64) return k4 ? f.template run<double, 4, 1>() : f.template run<double, 8, 1>();
+    return k4 ? f.template run<float, 4, 1>() : f.template run<float, 8, 1>();
+}
+
+struct WalkFn {
+    const Instance& I;
+    const WalkArgs& w;
+    template <typename T, int KMAX, int PPL>
+    hipError_t run() const { return dispatch_walk<T, KMAX, PPL>(I, w); }
+};
+struct BatchFn {
+    const Instance& I;
+    const BatchArgs& b;
+    int want_grad;
+    template <typename T, int KMAX, int PPL>
+    hipError_t run() const { return dispatch_batch<T, KMAX, PPL>(I, b, want_grad); }
+};
+struct OccupancyFn {
+    int* n;
+    int threads;
+    template <typename T, int KMAX, int PPL>
+    hipError_t run() const {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            n, reinterpret_cast<const void*>(&walk_small<T, KMAX, PPL, kPost | kRootFused | kPre | kGrad>),
+            threads, 0);
+    }
+};
+
+int ppl_of(const Instance& I) { return I.L.tile / kWave; }
+
 }  // namespace
 
+// Workgroups of the whole-tree kernel (with gradients) that one CU holds at once, for a
+// given number of patterns per lane; 0 if the runtime cannot tell.
+int small_blocks_per_cu(const Instance& I, int ppl) {
+    int n = 0;
+    const hipError_t e = with_variant(I, ppl, OccupancyFn{&n, kWave * I.d.n_categories});
+    return e == hipSuccess ? n : 0;
+}
 size_t build_tree_desc_small(const Instance& I, const WalkArgs& w, void* host_buf) {
     if (I.d.precision == HP_PREC_F64) {
         const WalkDev<double> a = make_desc<double>(I, w);
@@ -444,17 +599,11 @@ size_t build_tree_desc_small(const Instance& I, const WalkArgs& w, void* host_bu
 }
 
 hipError_t launch_batch_small(const Instance& I, const BatchArgs& b, int want_grad) {
-    const bool f64 = I.d.precision == HP_PREC_F64;
-    if (I.d.n_categories <= 4)
-        return f64 ? dispatch_batch<double, 4>(I, b, want_grad) : dispatch_batch<float, 4>(I, b, want_grad);
-    return f64 ? dispatch_batch<double, 8>(I, b, want_grad) : dispatch_batch<float, 8>(I, b, want_grad);
+    return with_variant(I, ppl_of(I), BatchFn{I, b, want_grad});
 }
 
 hipError_t launch_walk_small(const Instance& I, const WalkArgs& w) {
-    const bool f64 = I.d.precision == HP_PREC_F64;
-    if (I.d.n_categories <= 4)
-        return f64 ? dispatch_walk<double, 4>(I, w) : dispatch_walk<float, 4>(I, w);
-    return f64 ? dispatch_walk<double, 8>(I, w) : dispatch_walk<float, 8>(I, w);
+    return with_variant(I, ppl_of(I), WalkFn{I, w});
 }
 
 }  // namespace hp

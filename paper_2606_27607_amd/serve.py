@@ -123,7 +123,7 @@ class HipExecutor:
                    "out_dev": torch.empty(1 + nb, dtype=torch.float64, device=self.device),
                    "t_host": torch.empty(nb, dtype=torch.float64, pin_memory=True),
                    "out_host": torch.empty(1 + nb, dtype=torch.float64, pin_memory=True)}
-        return (s.precision, inst.query(_lib.HP_Q_STATE_PAD), len(d.rates))
+        return (s.precision, inst.query(_lib.HP_Q_STATE_PAD), len(d.rates), inst.query(_lib.HP_Q_TILE))
 
     def evict(self, s):
         if s.state is not None:

@@ -184,6 +184,74 @@ def test_bitwise_repeatable_and_device_path():
     assert torch.equal(out1, out2)
 
 
+# --------------------------------------------------------------- tile shapes (4-state path)
+
+@pytest.fixture
+def force_small_ppl(monkeypatch):
+    """Force the 4-state traversal tile (64 or 128 patterns per workgroup) for instances
+    created inside the test; the library reads the override at hp_create."""
+    def force(ppl):
+        monkeypatch.setenv("HIPPHYLO_SMALL_PPL", str(ppl))
+    return force
+
+
+@pytest.mark.parametrize("ppl", [1, 2])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("kind,n,npat,K,seed", [("gtr", 31, 333, 4, 1), ("hky", 5, 129, 3, 2),
+                                                ("gtr", 70, 1, 4, 3), ("gtr", 17, 4100, 8, 4)])
+def test_tile_shapes_match_oracle(force_small_ppl, ppl, precision, kind, n, npat, K, seed):
+    """Both tiles, with ragged last tiles (333 = 2*128 + 77, 129 = 128 + 1, one pattern) and
+    K = 3 and 8 categories, against the oracle; whole-tree and operation-level paths."""
+    from paper_2606_27607_amd import _lib
+    force_small_ppl(ppl)
+    wl = synth.make_workload(kind, n, npat, seed=seed, n_categories=K, unknown_frac=0.05)
+    inst = make_instance(wl, precision, "every_k", 2)
+    assert inst.query(_lib.HP_Q_TILE) == 64 * ppl
+    assert inst.query(_lib.HP_Q_BLOCKS) == -(-npat // (64 * ppl))
+    assert inst.query(_lib.HP_Q_PATTERN_PAD) % 128 == 0
+    lnl, g = inst.evaluate(wl.t)
+    lnl_o, _, g_o = oracle_eval(wl)
+    tol = (1e-12, 1e-11) if precision == "f64" else (1e-5, 1e-3)
+    assert rel(lnl, lnl_o) < tol[0] and grad_err(g, g_o) < tol[1]
+    nb = 2 * n - 2
+    inst.update_matrices(np.arange(nb), wl.t[:nb])
+    inst.update_post(post_ops(wl.tree.children, n, rescale=1))
+    lnl2, site = inst.root_lnl(nb, site=True)
+    _, site_o, _ = oracle_eval(wl, want_grad=False)
+    assert rel(lnl2, lnl_o) < tol[0]
+    assert np.allclose(site[:npat], site_o, rtol=tol[0] * 10, atol=0)
+
+
+def test_tile_choice_and_batch_tile_check(force_small_ppl):
+    """The automatic tile fills whole rounds: 131,072 patterns (2,048 one-pattern
+    workgroups, more than the device holds at once in FP32) take the two-pattern tile, and
+    instances of different tiles are not batched together."""
+    import ctypes
+
+    import torch
+    from paper_2606_27607_amd import Instance, _lib
+    big = Instance(8, 131072, 4, 4, precision="f32", scaling="every_k", scale_period=4)
+    small = Instance(8, 1000, 4, 4, precision="f32", scaling="every_k", scale_period=4)
+    assert big.query(_lib.HP_Q_TILE) == 128 and small.query(_lib.HP_Q_TILE) == 64
+    wl = synth.make_workload("gtr", 8, 1000, seed=3)
+    force_small_ppl(2)
+    a = make_instance(wl, "f32", "every_k", 4)
+    force_small_ppl(1)
+    b = make_instance(wl, "f32", "every_k", 4)
+    t = torch.tensor(np.r_[wl.t[:14], 0.0], dtype=torch.float64, device="cuda")
+    out = torch.zeros(64, dtype=torch.float64, device="cuda")
+    lib = _lib.load()
+    rc = lib.hp_batch_evaluate_device((ctypes.c_void_p * 2)(a._inst.value, b._inst.value),
+                                      (ctypes.c_void_p * 2)(t.data_ptr(), t.data_ptr()),
+                                      (ctypes.c_void_p * 2)(out.data_ptr(), out.data_ptr()), 2, 1, None)
+    assert rc == _lib.HP_ERR_UNSUPPORTED
+    la, ga = a.evaluate(wl.t)
+    lb, gb = b.evaluate(wl.t)
+    assert rel(la, lb) < 1e-6 and grad_err(ga, gb) < 1e-4
+    for inst in (big, small, a, b):
+        inst.close()
+
+
 # --------------------------------------------------------------- full-size configurations
 
 @pytest.mark.parametrize("precision,tol_l,tol_g", [("f32", 1e-5, 1e-3), ("f64", 1e-12, 1e-10)])
