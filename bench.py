@@ -15,6 +15,7 @@ FP64 form and for the 64-taxon codon workload in FP32 / BF16 / FP16 / FP64 ("var
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -216,6 +217,131 @@ def measure_autograd(wl, precision: str, steps: int) -> dict:
             "modes": res}
 
 
+# 16-bit storage for the matrix-core classes: BF16, whose exponent range is FP32's.  FP16 runs
+# faster but flushes values below 2^-24 of a pattern's maximum; on large trees with very short
+# branches that can zero a site likelihood (HP_ERR_NUMERIC), which a server must not risk.
+SERVING_PRECISION = {4: "f32", 20: "bf16", 61: "bf16"}
+
+
+def _serving_client(c):
+    import synth
+    wl = synth.serving_workload(c)
+    return c, wl, synth.serving_requests(wl, c)
+
+
+def serving_inputs(n_clients: int, jobs: int):
+    """Every client's data set and requests, simulated in worker processes (forked before
+    this process touches the GPU), largest first so that the pool finishes together."""
+    import multiprocessing as mp
+
+    import synth
+    sizes = []
+    for c in range(n_clients):
+        d = synth.serving_dataset(c)
+        sizes.append((-d["n_tips"] * d["n_patterns"], c))
+    order = [c for _, c in sorted(sizes)]
+    with mp.get_context("fork").Pool(max(1, jobs)) as pool:
+        got = {c: (wl, reqs) for c, wl, reqs in pool.imap_unordered(_serving_client, order)}
+    return [got[c] for c in range(n_clients)]
+
+
+def serving_bench(inputs, loads=(0.5, 0.8, 1.0), seed: int = 20260055) -> dict:
+    """Many clients, continuous batching: isolated capacity, then Poisson arrivals at
+    fractions of it; latency from submission to result, alone-vs-mix equality, and the
+    oracle error on a stratified sample of clients."""
+    import numpy as np
+
+    from paper_2606_27607_amd.serve import Dataset, HipExecutor, Server
+
+    n_clients = len(inputs)
+    reqs = [(c, r) for c in range(n_clients) for r in range(len(inputs[c][1]))]
+    work_b, work_f = {}, {}
+    for c, (wl, _) in enumerate(inputs):
+        prec = SERVING_PRECISION[wl.n_states]
+        sp = 4 if wl.n_states <= 4 else (32 if wl.n_states <= 32 else 64)
+        work_b[c] = algorithmic_bytes(wl.n_tips, wl.n_patterns, sp if sp == 4 else wl.n_states,
+                                      wl.n_categories, ELEM[prec])
+        work_f[c] = algorithmic_flops(wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories)
+    import torch
+    torch.cuda.empty_cache()          # sessions allocate straight from the device
+    ex = HipExecutor(0)
+    srv = Server(executor=ex, precision=SERVING_PRECISION).start()
+    chunks = {c: srv.register(c, Dataset.from_workload(wl)) for c, (wl, _) in enumerate(inputs)}
+    # isolated: one request at a time, each client's session loaded by an untimed first call
+    t_start = time.perf_counter()
+    alone, service = {}, []
+    for c, (wl, ts) in enumerate(inputs):
+        srv.evaluate(c, ts[0])
+        for r in range(len(ts)):
+            s0 = time.perf_counter()
+            alone[(c, r)] = srv.evaluate(c, ts[r])
+            service.append(time.perf_counter() - s0)
+        if c % 16 == 15:
+            print(f"[bench] serving: isolated pass, {c + 1} clients done", file=sys.stderr, flush=True)
+    capacity = len(service) / sum(service)
+    isolated = {"requests_per_s": capacity, "p50_ms": 1000 * float(np.percentile(service, 50)),
+                "p99_ms": 1000 * float(np.percentile(service, 99)),
+                "seconds": time.perf_counter() - t_start, "evictions": srv.stats()["evictions"]}
+    rng = np.random.default_rng(seed)
+    mixes = []
+    mismatch = 0
+    for load in loads:
+        srv.reset_stats()
+        order = rng.permutation(len(reqs))
+        arrivals = np.cumsum(rng.exponential(1.0 / (load * capacity), len(reqs)))
+        futs = []
+        t0 = time.perf_counter()
+        for i, idx in enumerate(order):
+            while True:
+                d = t0 + arrivals[i] - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(min(d, 5e-4))
+            c, r = reqs[idx]
+            futs.append(((c, r), srv.submit(c, inputs[c][1][r])))
+        for key, f in futs:
+            lnl, g = f.result(timeout=300)
+            a_lnl, a_g = alone[key]
+            mismatch += int(not (lnl == a_lnl and np.array_equal(g, a_g)))
+        st = srv.stats()
+        span = st["requests_per_s"] and st["completed"] / st["requests_per_s"]
+        mixes.append({"load": load, "offered_requests_per_s": load * capacity,
+                      "requests_per_s": st["requests_per_s"], "p50_ms": st["p50_ms"],
+                      "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "mean_batch": st["mean_batch"],
+                      "batches": st["batches"], "max_concurrent_batches": st["max_concurrent_batches"],
+                      "evictions": st["evictions"],
+                      "algorithmic_GBs": sum(work_b[c] for c, _ in reqs) / span / 1e9,
+                      "algorithmic_TFLOPs": sum(work_f[c] for c, _ in reqs) / span / 1e12})
+        print(f"[bench] serving: load {load} done, p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
+    srv.close()
+    # lnL / gradient error of the served result against the stored oracle values
+    err = {}
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_serving.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+        for key, rec in gold.items():
+            c = int(key)
+            if c >= n_clients:
+                continue
+            lnl, g = alone[(c, rec["request"])]
+            gg = np.array(rec["grad"])
+            err[key] = {"states": rec["n_states"], "taxa": rec["n_tips"], "patterns": rec["n_patterns"],
+                        "precision": SERVING_PRECISION[rec["n_states"]],
+                        "lnl_rel": abs(lnl - rec["lnl"]) / abs(rec["lnl"]),
+                        "grad_maxabs_over_maxabs": float(np.max(np.abs(g - gg)) / np.max(np.abs(gg)))}
+    kinds = collections.Counter(inputs[c][0].n_states for c in range(n_clients))
+    return {"clients": n_clients, "requests": len(reqs),
+            "state_spaces": {str(k): v for k, v in sorted(kinds.items())},
+            "precision": {str(k): v for k, v in SERVING_PRECISION.items()},
+            "pattern_chunked_clients": sum(1 for v in chunks.values() if v > 1),
+            "memory_budget_bytes": srv.memory_budget,
+            "isolated": isolated, "mix": mixes, "mix_vs_alone_mismatches": mismatch,
+            "error_vs_oracle_sample": err,
+            "arrivals": "Poisson, rate = load x isolated capacity, requests in random order"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +353,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=50)
+    ap.add_argument("--serving", action="store_true",
+                    help="also run the serving benchmark (64 clients x 8 requests, mixed state "
+                         "spaces, Poisson arrivals)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving benchmark")
+    ap.add_argument("--serving-clients", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference for scaling HBM byte counters")
@@ -247,6 +378,17 @@ def main():
         sys.exit(2)
 
     import synth
+
+    serving_data = None
+    if args.serving or args.serving_only:
+        # simulated before anything touches the GPU: the worker processes are forks of this one
+        print(f"[bench] serving: simulating {args.serving_clients} client data sets", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        serving_data = serving_inputs(args.serving_clients, min(16, len(os.sched_getaffinity(0))))
+        print(f"[bench] serving: data ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(serving_data)}), flush=True)
+        return
 
     print(f"[bench] workload {args.workload} {args.precision}", file=sys.stderr, flush=True)
     wl = synth.config_workload(args.workload)
@@ -281,6 +423,9 @@ def main():
         print("[bench] autograd modes", file=sys.stderr, flush=True)
         line["autograd"] = [measure_autograd(synth.config_workload("nuc256"), "f32", 20),
                             measure_autograd(synth.config_workload("codon32"), "bf16", 20)]
+    if serving_data is not None:
+        line["serving"] = serving_bench(serving_data)
+        serving_data = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, wl.n_patterns))

@@ -39,7 +39,7 @@ class Instance:
     def __init__(self, n_tips: int, n_patterns: int, n_states: int, n_categories: int = 4, *,
                  precision: str = "f32", scaling: str = "every_k", scale_period: int = 4,
                  n_partials: int | None = None, n_matrices: int | None = None, n_eigen: int = 1,
-                 device: int = 0):
+                 device: int = 0, workspace_ptr: int | None = None):
         import torch
         self._lib = _lib.load()
         self.torch = torch
@@ -54,12 +54,16 @@ class Instance:
         nbytes = ctypes.c_size_t()
         check(self._lib, self._lib.hp_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value
-        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        # the caller may bring its own device memory (workspace_ptr, at least workspace_bytes,
+        # 256-byte aligned, outliving the instance); otherwise torch allocates it
+        self.workspace = (None if workspace_ptr is not None
+                          else torch.empty(nbytes.value, dtype=torch.uint8, device=self.device))
+        ws = workspace_ptr if workspace_ptr is not None else self.workspace.data_ptr()
         self._inst = ctypes.c_void_p()
         self.generation = 0  # bumped by every call that may change partials or matrices
         stream = torch.cuda.current_stream(self.device).cuda_stream
         check(self._lib, self._lib.hp_create(ctypes.byref(self.desc),
-                                             ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                             ctypes.c_void_p(ws), nbytes,
                                              ctypes.c_void_p(stream), ctypes.byref(self._inst)))
         self._stream = stream
 

@@ -82,6 +82,35 @@ def scaling_for(n_states):
     return ("every_k", 4) if n_states <= 4 else ("every_node", 1)
 
 
+class DeviceMemory:
+    """Session workspaces straight from hipMalloc / hipFree.  An evicted session's memory goes
+    back to the device at once; a caching allocator would keep it for its own reuse, and
+    sessions of very different sizes then fragment it until a large one no longer fits."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        _lib.load()                                   # torch first, then the runtime it loaded
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+        self.hip.hipMalloc.restype = ctypes.c_int
+        self.hip.hipFree.argtypes = [ctypes.c_void_p]
+        self.hip.hipFree.restype = ctypes.c_int
+
+    def alloc(self, nbytes: int) -> int:
+        p = ctypes.c_void_p()
+        with self.torch.cuda.device(self.device):
+            rc = self.hip.hipMalloc(ctypes.byref(p), ctypes.c_size_t(nbytes))
+        if rc != 0 or not p.value:
+            raise MemoryError(f"hipMalloc of {nbytes} bytes failed (hipError {rc})")
+        return p.value
+
+    def free(self, ptr: int) -> None:
+        with self.torch.cuda.device(self.device):
+            self.hip.hipFree(ctypes.c_void_p(ptr))
+
+
 class HipExecutor:
     """Device side of the server: instances, batched launches on per-class streams."""
 
@@ -92,6 +121,7 @@ class HipExecutor:
         self.device_index = device
         self.device = torch.device("cuda", device)
         self.streams = {}
+        self.memory = DeviceMemory(device)
 
     def free_memory(self):
         free, _ = self.torch.cuda.mem_get_info(self.device)
@@ -113,12 +143,19 @@ class HipExecutor:
         from .instance import Instance
         d = s.data
         sc = scaling_for(d.n_states)
-        inst = Instance(d.n_tips, d.n_patterns, d.n_states, len(d.rates), precision=s.precision,
-                        scaling=sc[0], scale_period=sc[1], device=self.device_index)
-        inst.load(d.tips, d.weights, d.V, d.Vinv, d.lam, d.pi, d.rates, d.cat_weights,
-                  children=d.children)
+        ptr = self.memory.alloc(s.footprint)
+        try:
+            inst = Instance(d.n_tips, d.n_patterns, d.n_states, len(d.rates), precision=s.precision,
+                            scaling=sc[0], scale_period=sc[1], device=self.device_index,
+                            workspace_ptr=ptr)
+            inst.load(d.tips, d.weights, d.V, d.Vinv, d.lam, d.pi, d.rates, d.cat_weights,
+                      children=d.children)
+        except BaseException:
+            torch.cuda.synchronize(self.device)
+            self.memory.free(ptr)
+            raise
         nb = 2 * d.n_tips - 2
-        s.state = {"inst": inst,
+        s.state = {"inst": inst, "ptr": ptr,
                    "t_dev": torch.empty(nb, dtype=torch.float64, device=self.device),
                    "out_dev": torch.empty(1 + nb, dtype=torch.float64, device=self.device),
                    "t_host": torch.empty(nb, dtype=torch.float64, pin_memory=True),
@@ -128,6 +165,10 @@ class HipExecutor:
     def evict(self, s):
         if s.state is not None:
             s.state["inst"].close()
+            # work on the session has completed (it is idle), but its uploads ran on the
+            # instance's stream: let the device drain before the memory is reused
+            self.torch.cuda.synchronize(self.device)
+            self.memory.free(s.state["ptr"])
         s.state = None
 
     def launch(self, key, items):
@@ -309,6 +350,15 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
+    def reset_stats(self):
+        """Start a new measurement window (counters, latencies, throughput span)."""
+        with self.cv:
+            self.latencies = []
+            self.completed = self.errors = self.batches = self.evictions = 0
+            self.batch_sizes = []
+            self.max_concurrent_batches = 0
+            self.t_first = self.t_last = None
+
     def stats(self):
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
         span = (self.t_last - self.t_first) if self.completed else 0.0
@@ -337,10 +387,28 @@ class Server:
                 if not self.pending and not self.inflight:
                     self.cv.wait(timeout=0.01)
                     continue
-            progressed = self._complete()
-            progressed |= self._dispatch()
+            try:
+                progressed = self._complete()
+                progressed |= self._dispatch()
+            except Exception as e:  # noqa: BLE001 - the loop must outlive any one failure
+                self._fail_everything(e)
+                progressed = True
             if not progressed:
                 time.sleep(50e-6)
+
+    def _fail_everything(self, err):
+        """An error outside any one request's scope: fail what is queued and in flight, free
+        the sessions' busy marks, and keep serving new requests."""
+        with self.cv:
+            for q in self.pending.values():
+                for req in q:
+                    self._fail(req, err)
+            self.pending.clear()
+            for _, _, items in self.inflight:
+                for s, req in items:
+                    s.busy = False
+                    self._fail(req, err)
+            self.inflight = []
 
     def _admit(self, s: _Session) -> bool:
         if s.resident:
@@ -362,7 +430,13 @@ class Server:
                 self.ex.evict(x)
                 self.used -= x.footprint
                 self.evictions += 1
-        s.key = self.ex.load(s)
+        try:
+            s.key = self.ex.load(s)
+        except Exception as e:  # noqa: BLE001 - fail this session's requests only
+            for req in self.pending.get(s, ()):
+                self._fail(req, e)
+            self.pending[s] = collections.deque()
+            return False
         self.used += s.footprint
         return True
 

@@ -146,3 +146,37 @@ def serving_dataset(client: int, rng_seed: int = SEED_BASE + 50, max_tips: int =
     p = int(round(np.exp(rng.uniform(np.log(100), np.log(max_patterns)))))
     kind = ["gtr", "aa", "gy94"][int(rng.integers(3))]
     return {"kind": kind, "n_tips": n, "n_patterns": p, "seed": int(rng.integers(2**31))}
+
+
+def serving_workload(client: int) -> Workload:
+    """The data set of one serving client (shape from :func:`serving_dataset`), branches
+    ~ Exp(mean 0.1), 4 gamma categories (alpha 0.5)."""
+    spec = serving_dataset(client)
+    return make_workload(spec["kind"], spec["n_tips"], spec["n_patterns"], branch_mean=0.1,
+                         seed=spec["seed"], name=f"serve{client}")
+
+
+def serving_requests(wl: Workload, client: int, n_requests: int = 8,
+                     rng_seed: int = SEED_BASE + 51) -> np.ndarray:
+    """Branch-length vectors [n_requests, 2N-2] of one client, as an MCMC proposal makes
+    them: the data set's branch lengths times exp(0.05 Z), Z ~ N(0, 1) per branch."""
+    rng = np.random.default_rng(np.random.SeedSequence([rng_seed, client]))
+    nb = 2 * wl.n_tips - 2
+    return wl.t[:nb][None, :] * np.exp(0.05 * rng.standard_normal((n_requests, nb)))
+
+
+def serving_oracle_sample(n_clients: int = 64) -> list:
+    """Clients whose first request is checked against the oracle: for each state space the
+    smallest data set and the one of median size (by taxa x patterns x states^2)."""
+    by_kind = {}
+    for c in range(n_clients):
+        spec = serving_dataset(c)
+        s = {"gtr": 4, "aa": 20, "gy94": 61}[spec["kind"]]
+        by_kind.setdefault(spec["kind"], []).append((spec["n_tips"] * spec["n_patterns"] * s * s, c))
+    out = []
+    for kind in ("gtr", "aa", "gy94"):
+        rows = sorted(by_kind.get(kind, []))
+        if rows:
+            out += sorted({rows[0][1], rows[(len(rows) - 1) // 2][1]})
+    return out
+

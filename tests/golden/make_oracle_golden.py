@@ -1,6 +1,10 @@
 """Write full-size FP64 oracle results for the named workloads (calls only oracle/ and synth/).
 
     python tests/golden/make_oracle_golden.py nuc8 nuc128 ...
+    python tests/golden/make_oracle_golden.py serving     # the serving clients' oracle sample
+
+For the serving sample, oracle_serving.json holds, per sampled client, lnL and every branch
+gradient at that client's first request.
 
 Each tests/golden/oracle_<name>.json holds the log-likelihood, every branch gradient and
 the site log-likelihoods of a fixed sample of patterns (every (P // 509)-th pattern plus
@@ -29,7 +33,28 @@ def sample_indices(n_patterns: int) -> np.ndarray:
     return np.unique(np.concatenate([idx, [n_patterns - 1]]))
 
 
+def serving():
+    out = {}
+    for c in synth.serving_oracle_sample():
+        t0 = time.time()
+        wl = synth.serving_workload(c)
+        t = synth.serving_requests(wl, c)[0]
+        lnl, _, grad = oracle.lnl_and_grad(wl.tree.children, wl.n_tips, np.r_[t, 0.0], wl.Q, wl.pi,
+                                           wl.rates, wl.cat_weights, wl.tips, wl.weights,
+                                           chunk=2000 if wl.n_states > 4 else 20000)
+        out[str(c)] = {"n_tips": wl.n_tips, "n_patterns": wl.n_patterns, "n_states": wl.n_states,
+                       "request": 0, "lnl": lnl, "grad": grad.tolist(),
+                       "oracle_seconds": time.time() - t0}
+        print(f"serving client {c}: N={wl.n_tips} P={wl.n_patterns} S={wl.n_states} "
+              f"lnL {lnl:.6f} in {time.time() - t0:.1f} s", flush=True)
+    with open(os.path.join(HERE, "oracle_serving.json"), "w") as f:
+        json.dump(out, f)
+
+
 def main(names):
+    if "serving" in names:
+        serving()
+        names = [n for n in names if n != "serving"]
     for name in names:
         t0 = time.time()
         wl = synth.config_workload(name)

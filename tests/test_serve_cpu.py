@@ -12,10 +12,13 @@ from paper_2606_27607_amd.serve import Dataset, Server
 
 
 class FakeExecutor:
-    def __init__(self, service_s=0.002, fail_clients=(), raise_on_launch=()):
+    def __init__(self, service_s=0.002, fail_clients=(), raise_on_launch=(), raise_on_load=(),
+                 raise_on_poll=0):
         self.service_s = service_s
         self.fail_clients = set(fail_clients)
         self.raise_on_launch = set(raise_on_launch)
+        self.raise_on_load = set(raise_on_load)
+        self.raise_on_poll = raise_on_poll            # polls that raise, counted down
         self.resident = set()
         self.used = 0
         self.budget = None
@@ -30,6 +33,8 @@ class FakeExecutor:
         return data.n_tips * data.n_patterns * 8
 
     def load(self, s):
+        if s.client in self.raise_on_load:
+            raise MemoryError("device allocation failed")
         with self.lock:
             assert s not in self.resident
             self.resident.add(s)
@@ -54,6 +59,9 @@ class FakeExecutor:
         return (time.perf_counter() + self.service_s, items)
 
     def poll(self, token):
+        if self.raise_on_poll > 0:
+            self.raise_on_poll -= 1
+            raise RuntimeError("device lost")
         t_done, items = token
         if time.perf_counter() < t_done:
             return None
@@ -180,3 +188,32 @@ def test_unknown_client_and_budget_checks():
     with pytest.raises(ValueError):
         srv.register(1, dataset(500, 2))                  # cannot be chunked below the cap
     srv.close()
+
+
+def test_load_failure_fails_only_that_session():
+    ex = FakeExecutor(raise_on_load={2})
+    with Server(memory_budget=10 ** 9, executor=ex) as srv:
+        for c in range(4):
+            srv.register(c, dataset(5, 30))
+        futs = {c: srv.submit(c, np.full(8, 0.1)) for c in range(4)}
+        with pytest.raises(MemoryError):
+            futs[2].result(timeout=10)
+        for c in (0, 1, 3):
+            assert futs[c].result(timeout=10)[0] == pytest.approx(0.8 * 30)
+        with pytest.raises(MemoryError):                 # still failing, still isolated
+            srv.evaluate(2, np.full(8, 0.1))
+        assert srv.evaluate(1, np.full(8, 0.2))[0] == pytest.approx(1.6 * 30)
+
+
+def test_loop_survives_unexpected_errors():
+    """An error outside any request (here: the completion poll raising) fails what is queued
+    and in flight, and the loop keeps serving new requests."""
+    ex = FakeExecutor(service_s=0.01, raise_on_poll=1)
+    with Server(memory_budget=10 ** 9, executor=ex) as srv:
+        for c in range(3):
+            srv.register(c, dataset(5, 30))
+        first = [srv.submit(c, np.full(8, 0.1)) for c in range(3)]
+        for f in first:
+            with pytest.raises(RuntimeError):
+                f.result(timeout=10)
+        assert srv.evaluate(0, np.full(8, 0.1))[0] == pytest.approx(0.8 * 30)
