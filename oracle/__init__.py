@@ -15,7 +15,10 @@ definitions are written out):
   inner product of pre- and post-order partials at every node (Key
   Improvements, Algorithmic advances; Ji et al. 2020);
 * the gradient with respect to every branch length as a pre . Q . post
-  "sandwich" in one pre-order traversal (Discussion).
+  "sandwich" in one pre-order traversal (Discussion);
+* the gradient with respect to every rate-matrix entry, with the derivative of each
+  transition matrix taken to first order (Key Improvements, Algorithmic advances;
+  random-effects substitution models), in ``rate_gradient.py``.
 
 Parity pins: each function is checked in ``tests/test_oracle_*.py`` against
 closed forms, brute-force summation, invariants and finite differences.
@@ -24,8 +27,10 @@ from .pruning import (
     transition_matrices, tip_partials, post_order, root_site_loglik, pre_order,
     branch_gradients, log_likelihood, lnl_and_grad, postorder_nodes,
 )
+from .rate_gradient import rate_matrix_gradient
 
 __all__ = [
     "transition_matrices", "tip_partials", "post_order", "root_site_loglik", "pre_order",
     "branch_gradients", "log_likelihood", "lnl_and_grad", "postorder_nodes",
+    "rate_matrix_gradient",
 ]

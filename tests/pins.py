@@ -5,6 +5,8 @@
 * ``brute_force_site_lik`` - the likelihood of each pattern as the explicit sum over every
                            assignment of states to internal nodes (the definition that
                            Felsenstein's pruning algorithm factorises);
+* ``brute_force_rate_gradient`` - the first-order rate-matrix gradient by the same
+                           enumeration, with each edge's matrix moved along r t E_ij P;
 * ``jc69_two_taxon``     - closed forms for two taxa under Jukes-Cantor;
 * ``reroot``             - re-rooting of a tree on another edge (reversible models leave
                            the likelihood unchanged).
@@ -70,6 +72,57 @@ def brute_force_site_lik(children, n_tips, t, Q, pi, rates, cat_weights, tips) -
             lik_k += term
         total += w * lik_k
     return total
+
+
+def brute_force_rate_gradient(children, n_tips, t, Q, pi, rates, cat_weights, tips, weights):
+    """sum_p c_p (dL_p / L_p) with every P_k(t_c) moved along r_k t_c E_ij P_k(t_c), by
+    explicit enumeration of internal states.
+
+    The likelihood is linear in each edge's matrix, so the derivative along that direction is
+    the sum over edges of the enumeration with that edge's factor P[x, y] replaced by
+    r t (E_ij P)[x, y] = r t [x == i] P[j, y].  Returns (G [S, S], L [P])."""
+    S = Q.shape[0]
+    root = 2 * n_tips - 2
+    internal = list(range(n_tips, 2 * n_tips - 1))
+    edges = [(v, int(c)) for v in internal for c in children[v]]
+    tips = np.asarray(tips)
+    n_pat = tips.shape[1]
+    L = np.zeros(n_pat)
+    dL = np.zeros((S, S, n_pat))
+
+    def factor(M, st_v, c):
+        """M[st_v, state of c] per pattern (a tip's unknown state sums the row)."""
+        if c >= n_tips:
+            return None
+        obs = tips[c]
+        row = M[st_v]
+        return np.where(obs < S, row[np.minimum(obs, S - 1)], row.sum())
+
+    for k, (r, w) in enumerate(zip(rates, cat_weights)):
+        Pk = {c: uniformized_P(Q, r * t[c]) for _, c in edges}
+        for assign in itertools.product(range(S), repeat=len(internal)):
+            st = dict(zip(internal, assign))
+            fac = {}
+            for v, c in edges:
+                f = factor(Pk[c], st[v], c)
+                fac[c] = np.full(n_pat, Pk[c][st[v], st[c]]) if f is None else f
+            term = np.full(n_pat, pi[st[root]])
+            for v, c in edges:
+                term = term * fac[c]
+            L += w * term
+            for v, c in edges:
+                rest = np.full(n_pat, pi[st[root]])
+                for v2, c2 in edges:
+                    if c2 != c:
+                        rest = rest * fac[c2]
+                # (E_ij P)[x, y] is nonzero only for x = i (the parent's state): row j of P
+                i = st[v]
+                for j in range(S):
+                    f = factor(Pk[c], j, c)
+                    fj = np.full(n_pat, Pk[c][j, st[c]]) if f is None else f
+                    dL[i, j] += w * r * t[c] * rest * fj
+    G = np.einsum("p,ijp->ij", np.asarray(weights, dtype=np.float64) / L, dL)
+    return G, L
 
 
 def jc69_two_taxon(d: float, rates, cat_weights):
