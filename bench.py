@@ -189,6 +189,68 @@ def measure(wl, precision: str, steps: int, warmup: int, latency_samples: int) -
     }
 
 
+def measure_rate_gradient(wl, precision: str, steps: int, warmup: int) -> dict:
+    """lnL + branch gradients + the first-order rate-matrix gradient per evaluation (4-state
+    path): throughput, traversal time against the plain evaluation's, error vs the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2606_27607_amd import Instance
+
+    N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
+    nb = 2 * N - 2
+    inst = Instance(N, P, S, K, precision=precision, scaling="every_k",
+                    scale_period=max(1, wl.meta.get("scale_every", 4)))
+    inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
+              children=wl.tree.children)
+    rng = np.random.default_rng(2)
+    n_sets = steps + warmup
+    t_all = wl.t[:nb][None, :] * np.exp(0.05 * rng.standard_normal((n_sets, nb)))
+    t_dev = torch.tensor(t_all, dtype=torch.float64, device=inst.device)
+    out = torch.empty((n_sets, 1 + nb + S * S), dtype=torch.float64, device=inst.device)
+    lnl, g, G = inst.evaluate_rate_gradient(wl.t)
+    err = {}
+    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{wl.name}_rate.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+        Go = np.array(gold["rate_grad"])
+        err = {"lnl_rel": abs(lnl - gold["lnl"]) / abs(gold["lnl"]),
+               "rate_grad_maxabs_over_maxabs": float(np.max(np.abs(G - Go)) / np.max(np.abs(Go))),
+               "reference": "FP64 oracle, full workload"}
+    res = {}
+    for form in ("plain", "rate_gradient"):
+        for i in range(warmup):
+            if form == "plain":
+                inst.evaluate_device(t_dev[i], out=out[i, : 1 + nb])
+            else:
+                inst.evaluate_rate_gradient_device(t_dev[i], out=out[i])
+        torch.cuda.synchronize()
+        inst.profile(True)
+        inst.profile_read()
+        t0 = time.perf_counter()
+        for i in range(warmup, n_sets):
+            if form == "plain":
+                inst.evaluate_device(t_dev[i], out=out[i, : 1 + nb])
+            else:
+                inst.evaluate_rate_gradient_device(t_dev[i], out=out[i])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = inst.profile_read()
+        inst.profile(False)
+        inst.status()
+        res[form] = {"evals_per_s": steps / el,
+                     "traversal_ms": prof["traversal"][0] / max(1, prof["traversal"][1])}
+    inst.close()
+    return {"workload": f"{wl.name}: {N} taxa, {P} patterns, S={S}", "precision": precision,
+            "evals_per_s": res["rate_gradient"]["evals_per_s"],
+            "traversal_ms": res["rate_gradient"]["traversal_ms"],
+            "plain_evals_per_s": res["plain"]["evals_per_s"],
+            "plain_traversal_ms": res["plain"]["traversal_ms"],
+            "overhead_vs_plain": res["plain"]["evals_per_s"] / res["rate_gradient"]["evals_per_s"] - 1.0,
+            "error_vs_oracle": err}
+
+
 def measure_autograd(wl, precision: str, steps: int) -> dict:
     """Forward + backward of BranchLengthLnL per mode (store / recompute / fused), ms per step."""
     import torch
@@ -420,6 +482,10 @@ def main():
                 p: {"speedup_vs_f32": by[(64, p)]["value"] / c32["value"],
                     "lnl_rel_err": by[(64, p)]["error_vs_oracle"].get("lnl_rel")}
                 for p in ("bf16", "f16") if (64, p) in by}
+        print("[bench] rate-matrix gradient", file=sys.stderr, flush=True)
+        line["rate_matrix_gradient"] = [measure_rate_gradient(synth.config_workload("nuc128"), p,
+                                                              max(10, args.steps // 2), 3)
+                                        for p in ("f32", "f64")]
         print("[bench] autograd modes", file=sys.stderr, flush=True)
         line["autograd"] = [measure_autograd(synth.config_workload("nuc256"), "f32", 20),
                             measure_autograd(synth.config_workload("codon32"), "bf16", 20)]

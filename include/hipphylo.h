@@ -232,6 +232,24 @@ int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, doub
  * matrices in between (the library cannot detect it). */
 int hp_gradients_device(hp_instance* inst, double* d_grad);
 
+/* Approximate gradient of lnL with respect to every entry Q_ij of the rate matrix of model
+ * slot 0, for random-effects substitution models (Key Improvements, Algorithmic advances:
+ * the gradient with respect to the rate-matrix entries, with the derivative of each matrix
+ * exponential taken to first order).  With dP_k(t)/dQ_ij ~= r_k t E_ij P_k(t) (E_ij: the
+ * matrix unit at (i, j)), each branch c contributes through its own matrix:
+ *     G_ij = sum_c t_c sum_p c_p [sum_k w_k r_k (top_c)_i (u_c)_j] / [sum_k w_k top_c . u_c]
+ * with u_c = P_k(t_c) post_c and top_c = pre_n o (P_k(t_s) post_s), n the parent and s the
+ * sibling of c.  Every entry is treated as free, the diagonal included; the client applies
+ * the chain rule to its model's parameters (and to the rate normalisation, if any).
+ * One whole-tree evaluation as hp_evaluate with want_grad = 1, plus G: out_lnl (1),
+ * out_grad (2N-2, by node) and out_rate_grad (S*S, row-major), host pointers, blocking.
+ * n_states <= 4 only (HP_ERR_UNSUPPORTED otherwise). */
+int hp_evaluate_rate_gradient(hp_instance* inst, const double* t, double* out_lnl, double* out_grad,
+                              double* out_rate_grad);
+/* The same, stream-ordered on device pointers: d_t (2N-2 FP64) and d_out (1 + 2N-2 + S*S FP64:
+ * lnL, branch gradients, G row-major).  Nothing is synchronised; errors via hp_status. */
+int hp_evaluate_rate_gradient_device(hp_instance* inst, const double* d_t, double* d_out);
+
 /* ---------------------------------------------------------------- batched evaluation
  * Whole-tree evaluations of up to HP_MAX_BATCH instances in one launch per kernel (matrix
  * assembly, traversal, reduction), for serving many clients.  The instances must share

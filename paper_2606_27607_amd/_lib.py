@@ -74,6 +74,8 @@ SIGNATURES = {
     "hp_evaluate": [_P, _P, _I, _P, _P],
     "hp_evaluate_device": [_P, _P, _I, _P],
     "hp_gradients_device": [_P, _P],
+    "hp_evaluate_rate_gradient": [_P, _P, _P, _P, _P],
+    "hp_evaluate_rate_gradient_device": [_P, _P, _P],
     "hp_batch_evaluate_device": [_P, _P, _P, _I, _I, _P],
     "hp_status": [_P],
     "hp_profile": [_P, _I],

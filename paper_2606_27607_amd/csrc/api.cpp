@@ -111,7 +111,8 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     l.mat_stride = (size_t)K * S_pad * S_pad;
     l.tip_stride = (size_t)K * (S + 1) * S_pad;
     l.eig_stride = (size_t)2 * S * S + S;
-    l.max_out = 1 + max_grad_slots(d);
+    // lnL, the branch gradients and, on the 4-state path, the rate-matrix gradient
+    l.max_out = 1 + max_grad_slots(d) + (S_pad == 4 ? kQSlots : 0);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -809,11 +810,16 @@ int hp_set_tree(hp_instance* inst, const int32_t* children) {
     return HP_OK;
 }
 
-static int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out) {
+static int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out,
+                            bool rate_grad = false) {
     const int N = I->d.n_tips;
     HP_HIP(I, HP_PMAT(*I, 0, nullptr, d_t, 2 * N - 2));
     hp::WalkArgs a;
     a.mode = want_grad ? (hp::kPost | hp::kRootFused | hp::kPre | hp::kGrad) : (hp::kPost | hp::kRootFused);
+    if (rate_grad) {
+        a.mode |= hp::kQGrad;
+        a.t_mat = d_t;
+    }
     a.tree = true;
     a.post_ops = I->at<int32_t>(I->L.tree_ops);
     a.n_post = I->tree_n_post;
@@ -821,7 +827,8 @@ static int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, doubl
     a.n_pre = want_grad ? I->tree_n_pre : 0;
     a.n_grad = want_grad ? 2 * N - 2 : 0;
     HP_HIP(I, HP_WALK(*I, a));
-    HP_HIP(I, HP_REDUCE(*I, 1 + a.n_grad, d_out));
+    const int S = I->d.n_states;
+    HP_HIP(I, HP_REDUCE(*I, 1 + a.n_grad + (rate_grad ? S * S : 0), d_out));
     return HP_OK;
 }
 
@@ -870,6 +877,50 @@ int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, doub
     if (rc) return rc;
     DeviceGuard g(I->d.device);
     return enqueue_evaluate(I, d_t, want_grad, d_out);
+}
+
+int hp_evaluate_rate_gradient(hp_instance* inst, const double* t, double* out_lnl, double* out_grad,
+                              double* out_rate_grad) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!t || !out_lnl || !out_grad || !out_rate_grad) return fail(I, HP_ERR_ARG, "NULL argument");
+    if (I->S_pad != 4) return fail(I, HP_ERR_UNSUPPORTED, "the rate-matrix gradient needs n_states <= 4");
+    int rc = check_eval_state(I);
+    if (rc) return rc;
+    const int nb = 2 * I->d.n_tips - 2, S = I->d.n_states;
+    for (int c = 0; c < nb; ++c)
+        if (!(t[c] >= 0.0) || !std::isfinite(t[c])) return fail(I, HP_ERR_VALUE, "branch length < 0 or not finite");
+    DeviceGuard g(I->d.device);
+    rc = upload(I, I->ws + I->L.t_stage, t, (size_t)nb * 8);
+    if (rc) return rc;
+    double* d_out = I->at<double>(I->L.results);
+    rc = enqueue_evaluate(I, I->at<double>(I->L.t_stage), 1, d_out, true);
+    if (rc) return rc;
+    const int n_out = 1 + nb + S * S;
+    HP_HIP(I, hipMemcpyAsync(I->host_out, d_out, (size_t)n_out * 8, hipMemcpyDeviceToHost, I->stream));
+    HP_HIP(I, hipStreamSynchronize(I->stream));
+    *out_lnl = I->host_out[0];
+    std::copy(I->host_out + 1, I->host_out + 1 + nb, out_grad);
+    std::copy(I->host_out + 1 + nb, I->host_out + n_out, out_rate_grad);
+    int32_t st = 0;
+    rc = read_status(I, &st);
+    if (rc) return rc;
+    if (st & hp::kStatusNumeric) {
+        *out_lnl = -INFINITY;
+        return fail(I, HP_ERR_NUMERIC, "a site likelihood was zero or not finite");
+    }
+    return HP_OK;
+}
+
+int hp_evaluate_rate_gradient_device(hp_instance* inst, const double* d_t, double* d_out) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!d_t || !d_out) return fail(I, HP_ERR_ARG, "NULL argument");
+    if (I->S_pad != 4) return fail(I, HP_ERR_UNSUPPORTED, "the rate-matrix gradient needs n_states <= 4");
+    int rc = check_eval_state(I);
+    if (rc) return rc;
+    DeviceGuard g(I->d.device);
+    return enqueue_evaluate(I, d_t, 1, d_out, true);
 }
 
 int hp_batch_evaluate_device(hp_instance* const* insts, const double* const* d_t, double* const* d_out,

@@ -32,7 +32,9 @@ enum WalkMode : int {
     kRootBuf = 4,     // integrate a stored post buffer (no post walk)
     kPre = 8,         // walk the pre-order list
     kGrad = 16,       // accumulate branch gradients during the pre-order walk
+    kQGrad = 32,      // with kGrad: also the first-order rate-matrix gradient (S <= 4)
 };
+constexpr int kQSlots = 16;        // reduction slots of the rate-matrix gradient (S_pad^2, S <= 4)
 
 struct Layout {
     // byte offsets into the workspace
@@ -180,6 +182,7 @@ struct WalkArgs {
     int eigen_idx = 0;
     int n_grad = 0;        // gradient slots; reduction rows hold 1 + n_grad values
     double* site = nullptr;
+    const double* t_mat = nullptr;  // kQGrad: branch length of each matrix slot
     // whole-tree evaluation (hp_set_tree's lists): for 4 < S the post buffers then hold
     // u_c = P_c post_c of each edge instead of post_c (see tree_mfma_body)
     bool tree = false;

@@ -122,6 +122,8 @@ struct WalkDev {
     int n_post, n_pre, root_buf;
     int N, P_pad, K, S, rescale_pre;
     int tree;               // whole-tree lists: pre-order partials are read once (see below)
+    const double* t_mat;    // kQGrad: branch length of each matrix slot
+    int q_slot;             // kQGrad: first reduction slot of the rate-matrix gradient
 };
 
 // What one child edge of an operation needs for each pattern slot of the lane: its tip
@@ -144,6 +146,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
     constexpr int TW = kWave * PPL;
     __shared__ int sh_e[2][2][KMAX][TW];
     __shared__ T sh_v[2][3][KMAX][TW];
+    __shared__ double sh_q[(MODE & kQGrad) ? KMAX : 1][kQSlots];
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const int p0 = block * TW + lane;
@@ -318,6 +321,10 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
         const int wave_b = K > 1 ? 1 : 0;
         const V4<T> none[PPL] = {};
         const int none_e[PPL] = {};
+        // kQGrad: the lane's share of sum_c t_c sum_p (c_p / den_p) w_k r_k top_c (x) u_c, with
+        // top_c = pre_parent o u_sibling and u_c = P_c post_c: exactly the vectors the gradient
+        // numerator uses, so the first-order rate-matrix gradient costs one outer product
+        T acc[(MODE & kQGrad) ? 4 : 1][(MODE & kQGrad) ? 4 : 1] = {};
         ChildIn<T, PPL> in1{}, in2{}, nx1{}, nx2{};
         V4<T> qin[PPL] = {}, qnx[PPL] = {};
         int pq1 = -1, pq2 = -1;                  // pre buffers the previous operation produced
@@ -426,6 +433,34 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                         tot = wave_sum(tot);
                         if (lane == 0) a.h.partials[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
                     }
+                    if constexpr ((MODE & kQGrad) != 0) {
+                        // every wave needs each pattern's category sum of the denominator
+#pragma unroll
+                        for (int j = 0; j < PPL; ++j) {
+                            const int l = lane + j * kWave;
+                            double den = 0.0;
+                            for (int kk = 0; kk < K; ++kk) den += double(sh_v[s][0][kk][l]);
+                            const double om = cp[j] == 0.0 ? 0.0 : cp[j] / den;
+                            if (g1 >= 0) {
+                                const T f = T(om * a.t_mat[m1]) * wrk;
+                                const T vv[4] = {va[j].x, va[j].y, va[j].z, va[j].w};
+                                const T uu[4] = {ua[j].x, ua[j].y, ua[j].z, ua[j].w};
+#pragma unroll
+                                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                                    for (int y = 0; y < 4; ++y) acc[x][y] += f * vv[x] * uu[y];
+                            }
+                            if (g2 >= 0) {
+                                const T f = T(om * a.t_mat[m2]) * wrk;
+                                const T vv[4] = {vb[j].x, vb[j].y, vb[j].z, vb[j].w};
+                                const T uu[4] = {ub[j].x, ub[j].y, ub[j].z, ub[j].w};
+#pragma unroll
+                                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                                    for (int y = 0; y < 4; ++y) acc[x][y] += f * vv[x] * uu[y];
+                            }
+                        }
+                    }
                 }
             }
             // in whole-tree evaluation a pre-order partial is read once, by its own node's
@@ -449,6 +484,23 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 in2 = nx2;
             }
         }
+        if constexpr ((MODE & kQGrad) != 0) {
+            // pattern sum over the wave, category sum over the workgroup, S x S slots
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    const double v = wave_sum(double(acc[x][y]));
+                    if (lane == 0) sh_q[k][4 * x + y] = v;
+                }
+            __syncthreads();
+            if (threadIdx.x < a.S * a.S) {
+                const int x = threadIdx.x / a.S, y = threadIdx.x % a.S;
+                double v = 0.0;
+                for (int kk = 0; kk < K; ++kk) v += sh_q[kk][4 * x + y];
+                a.h.partials[(size_t)(a.q_slot + threadIdx.x) * a.h.n_blocks + block] = v;
+            }
+        }
     }
 }
 
@@ -456,18 +508,18 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
 // (72 VGPRs; the compiler's own choice of 79 allows only 6, and a grid that just misses
 // full residency pays a second, nearly empty round), 4 with two (128 VGPRs).  FP64 keeps
 // the compiler's choice: fewer registers would spill.
-template <typename T, int PPL>
-constexpr int kSmallWavesPerEu = sizeof(T) == 4 ? (PPL == 1 ? 7 : 4) : 1;
+template <typename T, int PPL, int MODE>
+constexpr int kSmallWavesPerEu = (MODE & kQGrad) ? 1 : sizeof(T) == 4 ? (PPL == 1 ? 7 : 4) : 1;
 
 template <typename T, int KMAX, int PPL, int MODE>
-__global__ void __launch_bounds__(KMAX * kWave) __attribute__((amdgpu_waves_per_eu(kSmallWavesPerEu<T, PPL>)))
+__global__ void __launch_bounds__(KMAX * kWave) __attribute__((amdgpu_waves_per_eu(kSmallWavesPerEu<T, PPL, MODE>)))
 walk_small(const WalkDev<T> a) {
     walk_small_body<T, KMAX, PPL, MODE>(a, blockIdx.x);
 }
 
 // One launch over the tiles of several instances: block -> (instance, local block).
 template <typename T, int KMAX, int PPL, int MODE>
-__global__ void __launch_bounds__(KMAX * kWave) __attribute__((amdgpu_waves_per_eu(kSmallWavesPerEu<T, PPL>)))
+__global__ void __launch_bounds__(KMAX * kWave) __attribute__((amdgpu_waves_per_eu(kSmallWavesPerEu<T, PPL, MODE>)))
 walk_small_batched(const BatchArgs b) {
     const int i = batch_find(b.walk_off, b.n, blockIdx.x);
     const WalkDev<T> a = load_desc<WalkDev<T>>(b.walk[i]);
@@ -506,6 +558,8 @@ WalkDev<T> make_desc(const Instance& I, const WalkArgs& w) {
     a.S = I.d.n_states;
     a.rescale_pre = I.d.scaling != HP_SCALE_NONE;
     a.tree = w.tree ? 1 : 0;
+    a.t_mat = w.t_mat;
+    a.q_slot = 1 + w.n_grad;
     return a;
 }
 
@@ -521,6 +575,9 @@ hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
         case kPre: HP_LAUNCH(kPre); break;
         case kPre | kGrad: HP_LAUNCH(kPre | kGrad); break;
         case kPost | kRootFused | kPre | kGrad: HP_LAUNCH(kPost | kRootFused | kPre | kGrad); break;
+        case kPost | kRootFused | kPre | kGrad | kQGrad:
+            HP_LAUNCH(kPost | kRootFused | kPre | kGrad | kQGrad);
+            break;
         default: return hipErrorInvalidValue;
     }
 #undef HP_LAUNCH

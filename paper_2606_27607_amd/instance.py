@@ -209,6 +209,34 @@ class Instance:
                    ctypes.c_void_p(out.data_ptr()))
         return out
 
+    def evaluate_rate_gradient(self, t):
+        """(lnL, d lnL / d t_c for every branch, G): G[i, j] is the first-order approximation
+        of d lnL / d Q_ij for the rate matrix of model slot 0 (n_states <= 4)."""
+        self._bind_stream()
+        nb = 2 * self.n_tips - 2
+        S = self.desc.n_states
+        tt = _f64(np.asarray(t, dtype=np.float64)[:nb], nb)
+        out = np.zeros(1)
+        g = np.zeros(nb)
+        G = np.zeros(S * S)
+        self._call("hp_evaluate_rate_gradient", _ptr(tt), _ptr(out), _ptr(g), _ptr(G))
+        return float(out[0]), g, G.reshape(S, S)
+
+    def evaluate_rate_gradient_device(self, t, out=None):
+        """Stream-ordered form: t (CUDA FP64, 2N-2) -> out (1 + 2N-2 + S*S: lnL, branch
+        gradients, G row-major).  Call :meth:`status` to check errors."""
+        self._bind_stream()
+        torch = self.torch
+        nb = 2 * self.n_tips - 2
+        S = self.desc.n_states
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() >= nb):
+            raise ValueError("t must be a contiguous CUDA float64 tensor of 2N-2 branch lengths")
+        if out is None:
+            out = torch.empty(1 + nb + S * S, dtype=torch.float64, device=self.device)
+        self._call("hp_evaluate_rate_gradient_device", ctypes.c_void_p(t.data_ptr()),
+                   ctypes.c_void_p(out.data_ptr()))
+        return out
+
     def gradients_device(self, out=None):
         """Stream-ordered pre-order pass and all branch gradients from the post-order partials
         of the preceding evaluate_device(..., want_grad=False); returns a CUDA float64 tensor."""

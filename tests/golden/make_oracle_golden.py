@@ -2,6 +2,7 @@
 
     python tests/golden/make_oracle_golden.py nuc8 nuc128 ...
     python tests/golden/make_oracle_golden.py serving     # the serving clients' oracle sample
+    python tests/golden/make_oracle_golden.py nuc8_rate nuc128_rate   # rate-matrix gradients
 
 For the serving sample, oracle_serving.json holds, per sampled client, lnL and every branch
 gradient at that client's first request.
@@ -51,10 +52,30 @@ def serving():
         json.dump(out, f)
 
 
+def rate_gradient(names):
+    """oracle_<name>_rate.json: the first-order rate-matrix gradient at the workload's own
+    branch lengths (4-state workloads)."""
+    for name in names:
+        t0 = time.time()
+        wl = synth.config_workload(name)
+        lnl, G = oracle.rate_matrix_gradient(wl.tree.children, wl.n_tips, wl.t, wl.Q, wl.pi, wl.rates,
+                                             wl.cat_weights, wl.tips, wl.weights, chunk=10000)
+        out = {"workload": name, "n_tips": wl.n_tips, "n_patterns": wl.n_patterns,
+               "n_states": wl.n_states, "lnl": lnl, "rate_grad": G.tolist(), "Q": wl.Q.tolist(),
+               "oracle_seconds": time.time() - t0}
+        with open(os.path.join(HERE, f"oracle_{name}_rate.json"), "w") as f:
+            json.dump(out, f)
+        print(f"{name} rate gradient in {time.time() - t0:.1f} s", flush=True)
+
+
 def main(names):
     if "serving" in names:
         serving()
         names = [n for n in names if n != "serving"]
+    rate = [n[: -len("_rate")] for n in names if n.endswith("_rate")]
+    if rate:
+        rate_gradient(rate)
+        names = [n for n in names if not n.endswith("_rate")]
     for name in names:
         t0 = time.time()
         wl = synth.config_workload(name)

@@ -1,0 +1,89 @@
+"""GPU parity of the first-order rate-matrix gradient (4-state path) against the oracle:
+small trees over state counts, category counts and both tile shapes, the full-size
+128-taxon workload against its stored oracle result, and the identity along Q at full size."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import announce, golden, grad_err, make_instance, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": (1e-12, 1e-10), "f32": (1e-5, 1e-3)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle(wl, t=None):
+    return oracle.rate_matrix_gradient(wl.tree.children, wl.n_tips, wl.t if t is None else t, wl.Q, wl.pi,
+                                       wl.rates, wl.cat_weights, wl.tips, wl.weights)
+
+
+def _g_err(G, Go):
+    return float(np.max(np.abs(G - Go)) / np.max(np.abs(Go)))
+
+
+@pytest.mark.parametrize("ppl", [1, 2])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("kind,n,npat,K,seed", [("gtr", 20, 700, 4, 1), ("hky", 7, 129, 1, 2),
+                                                ("bin", 9, 200, 3, 3), ("three", 6, 65, 8, 4),
+                                                ("gtr", 2, 40, 4, 5)])
+def test_matches_oracle(monkeypatch, ppl, precision, kind, n, npat, K, seed):
+    monkeypatch.setenv("HIPPHYLO_SMALL_PPL", str(ppl))
+    wl = synth.make_workload(kind, n, npat, seed=seed, n_categories=K, unknown_frac=0.05)
+    inst = make_instance(wl, precision, "every_k", 2)
+    lnl, g, G = inst.evaluate_rate_gradient(wl.t)
+    lnl_o, G_o = _oracle(wl)
+    _, _, g_o = oracle.lnl_and_grad(wl.tree.children, n, wl.t, wl.Q, wl.pi, wl.rates, wl.cat_weights,
+                                    wl.tips, wl.weights)
+    tl, tg = TOL[precision]
+    assert G.shape == (wl.n_states, wl.n_states)
+    assert rel(lnl, lnl_o) < tl and grad_err(g, g_o) < tg
+    assert _g_err(G, G_o) < tg
+    # the same lnL and branch gradients as the plain evaluation
+    lnl2, g2 = inst.evaluate(wl.t)
+    assert rel(lnl, lnl2) < tl * 1e-2 and grad_err(g, g2) < tg * 1e-2
+
+
+def test_device_form_and_errors():
+    import torch
+    from paper_2606_27607_amd import HPError, _lib
+    wl = synth.make_workload("gtr", 11, 300, seed=6)
+    inst = make_instance(wl, "f64", "every_node")
+    lnl, g, G = inst.evaluate_rate_gradient(wl.t)
+    nb = 2 * wl.n_tips - 2
+    t = torch.tensor(wl.t[:nb], dtype=torch.float64, device="cuda")
+    out = inst.evaluate_rate_gradient_device(t)
+    torch.cuda.synchronize()
+    inst.status()
+    o = out.cpu().numpy()
+    assert o[0] == lnl and np.array_equal(o[1:1 + nb], g) and np.array_equal(o[1 + nb:].reshape(4, 4), G)
+    codon = synth.make_workload("gy94", 4, 20, seed=7)
+    ci = make_instance(codon, "f32", "every_node")
+    with pytest.raises(HPError) as e:
+        ci.evaluate_rate_gradient(codon.t)
+    assert e.value.code == _lib.HP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_nuc128_full_size(precision):
+    gold = golden("nuc128_rate")
+    if gold is None:
+        pytest.skip("tests/golden/oracle_nuc128_rate.json not generated")
+    wl = synth.config_workload("nuc128")
+    announce(f"nuc128 rate gradient {precision}")
+    inst = make_instance(wl, precision, "every_k", 4)
+    lnl, g, G = inst.evaluate_rate_gradient(wl.t)
+    Go = np.array(gold["rate_grad"])
+    tl, tg = TOL[precision]
+    assert rel(lnl, gold["lnl"]) < tl
+    assert _g_err(G, Go) < tg
+    # along Q the first-order derivative is exact: sum_ij Q_ij G_ij = sum_c t_c g_c
+    nb = 2 * wl.n_tips - 2
+    assert rel(float(np.sum(wl.Q * G)), float(np.dot(wl.t[:nb], g))) < (1e-9 if precision == "f64" else 1e-4)
