@@ -83,13 +83,17 @@ typedef struct hp_desc {
     int32_t n_patterns;    /* P >= 1                                                    */
     int32_t n_states;      /* S in [2, 64]                                              */
     int32_t n_categories;  /* K in [1, 8]                                               */
-    int32_t n_partials;    /* internal partial buffers (>= N-1 for hp_set_tree)         */
+    int32_t n_partials;    /* post-order partial buffers (>= N-1 for hp_set_tree)       */
     int32_t n_matrices;    /* transition-matrix slots (>= 2N-2 for hp_set_tree)         */
     int32_t n_eigen;       /* eigensystem / frequency slots, >= 1                       */
     int32_t precision;     /* HP_PREC_*                                                 */
     int32_t scaling;       /* HP_SCALE_*                                                */
     int32_t scale_period;  /* k for HP_SCALE_EVERY_K_LEVELS (>= 1), ignored otherwise    */
     int32_t device;        /* HIP device ordinal the workspace lives on                 */
+    int32_t n_pre_partials;/* pre-order partial buffers; 0 means n_partials.  hp_set_tree
+                              reuses them as the pre-order walk frees them and needs only
+                              hp_plan_pre_buffers() of them (about the tree's height), so
+                              a whole-tree instance can size its workspace with that      */
 } hp_desc;
 
 typedef struct hp_instance hp_instance;
@@ -210,6 +214,12 @@ int hp_set_tree(hp_instance* inst, const int32_t* children);
  * (parents first).  Touches no device; the error message is read with hp_last_error(NULL). */
 int hp_plan_tree(int n_tips, const int32_t* children, int scaling, int scale_period,
                  int32_t* out_post_ops, int32_t* out_pre_ops);
+
+/* Host-only: the number of pre-order buffers hp_set_tree's operation lists use for this
+ * tree.  A pre-order partial lives from its parent's operation to its own, and the list
+ * visits the tree depth-first, so buffers are handed out from a free list and the count is
+ * bounded by the tree's height + 1 (the whole-tree lists need it in n_pre_partials). */
+int hp_plan_pre_buffers(int n_tips, const int32_t* children, int* out_count);
 
 /* One full evaluation on the tree of hp_set_tree with model slot 0: transition matrices
  * for all 2N-2 branches from t (FP64, 2N-2 values, indexed by node), post-order partials,

@@ -41,7 +41,7 @@ HP_Q_TILE = 6
 class hp_desc(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "n_tips", "n_patterns", "n_states", "n_categories", "n_partials", "n_matrices", "n_eigen",
-        "precision", "scaling", "scale_period", "device")]
+        "precision", "scaling", "scale_period", "device", "n_pre_partials")]
 
 
 POST_OP_FIELDS = ("dest", "child1", "mat1", "child2", "mat2", "rescale")
@@ -71,6 +71,7 @@ SIGNATURES = {
     "hp_pre_gradients": [_P, _P, _I, _I, _I, _P, _I],
     "hp_set_tree": [_P, _P],
     "hp_plan_tree": [_I, _P, _I, _I, _P, _P],
+    "hp_plan_pre_buffers": [_I, _P, ctypes.POINTER(ctypes.c_int)],
     "hp_evaluate": [_P, _P, _I, _P, _P],
     "hp_evaluate_device": [_P, _P, _I, _P],
     "hp_gradients_device": [_P, _P],
@@ -121,3 +122,14 @@ def check(lib, rc: int, inst=None) -> int:
     if rc != HP_OK:
         raise HPError(rc, last_error(lib, inst))
     return rc
+
+
+def plan_pre_buffers(children) -> int:
+    """Pre-order buffers the whole-tree operation lists need for this children table."""
+    import numpy as np
+    lib = load()
+    ch = np.ascontiguousarray(np.asarray(children, dtype=np.int32))
+    n = ctypes.c_int()
+    check(lib, lib.hp_plan_pre_buffers((ch.shape[0] + 1) // 2, ctypes.c_void_p(ch.ctypes.data),
+                                       ctypes.byref(n)))
+    return n.value

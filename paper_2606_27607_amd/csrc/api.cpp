@@ -62,6 +62,7 @@ int check_desc(const hp_desc* d) {
         return fail(nullptr, HP_ERR_UNSUPPORTED, "n_categories must be in [1, 8]");
     if (d->n_partials < 1 || d->n_matrices < 1 || d->n_eigen < 1)
         return fail(nullptr, HP_ERR_ARG, "n_partials, n_matrices and n_eigen must be >= 1");
+    if (d->n_pre_partials < 0) return fail(nullptr, HP_ERR_ARG, "n_pre_partials must be >= 0");
     if (d->precision < HP_PREC_F64 || d->precision > HP_PREC_F16)
         return fail(nullptr, HP_ERR_ARG, "unknown precision");
     if (d->scaling < HP_SCALE_NONE || d->scaling > HP_SCALE_EVERY_K_LEVELS)
@@ -84,6 +85,8 @@ int max_grad_slots(const hp_desc& d) {
 }
 
 int max_ops(const hp_desc& d) { return 4 * std::max(d.n_partials, d.n_tips) + 4; }
+
+int n_pre(const hp_desc& d) { return d.n_pre_partials > 0 ? d.n_pre_partials : d.n_partials; }
 
 }  // namespace
 
@@ -123,7 +126,7 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     l.pweights = take((size_t)P_pad * 8);
     l.post = take(np * l.post_stride * elem);
     l.post_exp = take(np * P_pad * 4);
-    l.pre = take(np * l.post_stride * elem);
+    l.pre = take((size_t)n_pre(d) * l.post_stride * elem);
     l.mats = take(nm * l.mat_stride * celem);
     if (mfma) l.matsT = take(nm * l.mat_stride * celem);
     if (lowp) {  // hi and lo 16-bit parts of P and P^T (lo only used for BF16)
@@ -628,13 +631,13 @@ static int check_pre_ops(Instance* I, const hp_pre_op* ops, int count, int n_gra
     std::vector<char> seen(std::max(n_grad, 0), 0);
     for (int i = 0; i < count; ++i) {
         const hp_pre_op& o = ops[i];
-        if (o.parent_pre >= I->d.n_partials) return fail(I, HP_ERR_INDEX, "parent_pre out of range");
+        if (o.parent_pre >= n_pre(I->d)) return fail(I, HP_ERR_INDEX, "parent_pre out of range");
         int rc = check_child(I, o.child1_post, "child1_post");
         if (!rc) rc = check_child(I, o.child2_post, "child2_post");
         if (!rc) rc = check_mat(I, o.mat1);
         if (!rc) rc = check_mat(I, o.mat2);
         if (rc) return rc;
-        if (o.child1_pre >= I->d.n_partials || o.child2_pre >= I->d.n_partials)
+        if (o.child1_pre >= n_pre(I->d) || o.child2_pre >= n_pre(I->d))
             return fail(I, HP_ERR_INDEX, "child pre buffer out of range");
         for (int g : {o.grad1, o.grad2}) {
             if (g < 0 || n_grad < 0) continue;
@@ -699,7 +702,7 @@ int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int fre
 // evaluation: post-order by depth-first search from the root (children before parents),
 // the rescaling plan, and the pre-order list (parents before children).  Host only.
 static int plan_tree(Instance* I, int N, const int32_t* children, int scaling, int period,
-                     std::vector<int32_t>* post, std::vector<int32_t>* pre) {
+                     std::vector<int32_t>* post, std::vector<int32_t>* pre, int* n_pre_buffers = nullptr) {
     const int root = 2 * N - 2, n_nodes = 2 * N - 1;
     std::vector<int> parent(n_nodes, -1);
     for (int v = 0; v < n_nodes; ++v) {
@@ -754,12 +757,28 @@ static int plan_tree(Instance* I, int N, const int32_t* children, int scaling, i
         run[v] = resc ? 0 : r;
         post->insert(post->end(), {v, a, a, b, b, resc});
     }
+    // pre-order: parents first (reversed post-order, a depth-first walk).  A pre-order
+    // partial lives from its parent's operation to its own, so buffers come from a free
+    // list: the children's buffers are taken before the parent's is given back (an
+    // operation never writes the buffer it reads), and the live set stays within the
+    // tree's height + 1.
+    std::vector<int> buf(n_nodes, -1), free_list;
+    int n_buf = 0;
+    auto take = [&]() {
+        if (free_list.empty()) return n_buf++;
+        const int b = free_list.back();
+        free_list.pop_back();
+        return b;
+    };
     for (auto it = order.rbegin(); it != order.rend(); ++it) {
         const int v = *it;
         const int a = children[2 * v], b = children[2 * v + 1];
-        pre->insert(pre->end(), {v == root ? -1 : v - N, a, a, a >= N ? a - N : -1, a, b, b,
-                                 b >= N ? b - N : -1, b});
+        if (a >= N) buf[a] = take();
+        if (b >= N) buf[b] = take();
+        pre->insert(pre->end(), {v == root ? -1 : buf[v], a, a, buf[a], a, b, b, buf[b], b});
+        if (v != root) free_list.push_back(buf[v]);
     }
+    if (n_pre_buffers) *n_pre_buffers = std::max(1, n_buf);
     return HP_OK;
 }
 
@@ -778,6 +797,12 @@ int hp_plan_tree(int n_tips, const int32_t* children, int scaling, int scale_per
     return HP_OK;
 }
 
+int hp_plan_pre_buffers(int n_tips, const int32_t* children, int* out_count) {
+    if (n_tips < 2 || !children || !out_count) return fail(nullptr, HP_ERR_ARG, "bad argument");
+    std::vector<int32_t> post, pre;
+    return plan_tree(nullptr, n_tips, children, HP_SCALE_NONE, 1, &post, &pre, out_count);
+}
+
 int hp_set_tree(hp_instance* inst, const int32_t* children) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
@@ -786,8 +811,11 @@ int hp_set_tree(hp_instance* inst, const int32_t* children) {
     if (I->d.n_partials < N - 1) return fail(I, HP_ERR_ARG, "n_partials < n_tips - 1");
     if (I->d.n_matrices < 2 * N - 2) return fail(I, HP_ERR_ARG, "n_matrices < 2 n_tips - 2");
     std::vector<int32_t> post, pre;
-    int rc = plan_tree(I, N, children, I->d.scaling, I->d.scale_period, &post, &pre);
+    int need = 0;
+    int rc = plan_tree(I, N, children, I->d.scaling, I->d.scale_period, &post, &pre, &need);
     if (rc) return rc;
+    if (need > n_pre(I->d))
+        return fail(I, HP_ERR_ARG, "n_pre_partials is smaller than hp_plan_pre_buffers for this tree");
     DeviceGuard g(I->d.device);
     int32_t* dst = I->at<int32_t>(I->L.tree_ops);
     rc = upload(I, dst, post.data(), post.size() * 4);

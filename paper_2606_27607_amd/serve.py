@@ -111,8 +111,53 @@ class DeviceMemory:
             self.hip.hipFree(ctypes.c_void_p(ptr))
 
 
+class Arena:
+    """Session workspaces carved out of one device allocation (first fit over a sorted free
+    list, neighbours coalesced, 256-byte granules).  Evicting a session returns its range
+    here and never to the runtime: freeing device memory synchronises the whole device,
+    which would stall every batch in flight.  alloc raises MemoryError when no free range
+    is large enough; the server then evicts more idle sessions."""
+
+    GRAIN = 256
+
+    def __init__(self, base: int, nbytes: int):
+        self.base = base
+        self.size = nbytes // self.GRAIN * self.GRAIN
+        self.free = [(0, self.size)]                # (offset, length), sorted by offset
+
+    def alloc(self, nbytes: int) -> int:
+        n = -(-nbytes // self.GRAIN) * self.GRAIN
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + n, ln - n)
+                return self.base + off
+        raise MemoryError(f"no free range of {n} bytes (largest {self.largest()})")
+
+    def release(self, ptr: int, nbytes: int) -> None:
+        off = ptr - self.base
+        n = -(-nbytes // self.GRAIN) * self.GRAIN
+        import bisect
+        i = bisect.bisect_left(self.free, (off, 0))
+        self.free.insert(i, (off, n))
+        # coalesce with the right, then the left neighbour
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:
+            self.free[i] = (off, n + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    def largest(self) -> int:
+        return max((ln for _, ln in self.free), default=0)
+
+
 class HipExecutor:
     """Device side of the server: instances, batched launches on per-class streams."""
+
+    STREAMS_PER_CLASS = 4
 
     def __init__(self, device: int = 0):
         import torch
@@ -121,11 +166,32 @@ class HipExecutor:
         self.device_index = device
         self.device = torch.device("cuda", device)
         self.streams = {}
+        self.turn = collections.Counter()
         self.memory = DeviceMemory(device)
+        self.arena = None
+
+    def reserve(self, nbytes: int) -> None:
+        """Take the sessions' device memory once, up front."""
+        if self.arena is None:
+            self.arena = Arena(self.memory.alloc(nbytes), nbytes)
+
+    def close(self) -> None:
+        """Give the arena back to the device (every session must have been evicted)."""
+        if self.arena is not None:
+            self.torch.cuda.synchronize(self.device)
+            self.memory.free(self.arena.base)
+            self.arena = None
 
     def free_memory(self):
         free, _ = self.torch.cuda.mem_get_info(self.device)
         return free
+
+    @staticmethod
+    def pre_buffers(data: Dataset) -> int:
+        """Pre-order buffers the session's tree needs (the walk reuses them: ~ tree height)."""
+        if getattr(data, "_n_pre", None) is None:
+            data._n_pre = _lib.plan_pre_buffers(data.children)
+        return data._n_pre
 
     def footprint(self, data: Dataset, precision: str) -> int:
         sc = scaling_for(data.n_states)
@@ -133,7 +199,8 @@ class HipExecutor:
                          n_categories=len(data.rates), n_partials=data.n_tips - 1,
                          n_matrices=2 * data.n_tips - 2, n_eigen=1,
                          precision=_lib.PRECISIONS[precision], scaling=_lib.SCALINGS[sc[0]],
-                         scale_period=sc[1], device=self.device_index)
+                         scale_period=sc[1], device=self.device_index,
+                         n_pre_partials=self.pre_buffers(data))
         n = ctypes.c_size_t()
         _lib.check(self.lib, self.lib.hp_workspace_bytes(ctypes.byref(d), ctypes.byref(n)))
         return n.value
@@ -143,16 +210,18 @@ class HipExecutor:
         from .instance import Instance
         d = s.data
         sc = scaling_for(d.n_states)
-        ptr = self.memory.alloc(s.footprint)
+        if self.arena is None:
+            raise RuntimeError("HipExecutor.reserve was not called")
+        ptr = self.arena.alloc(s.footprint)
         try:
             inst = Instance(d.n_tips, d.n_patterns, d.n_states, len(d.rates), precision=s.precision,
                             scaling=sc[0], scale_period=sc[1], device=self.device_index,
-                            workspace_ptr=ptr)
+                            workspace_ptr=ptr, n_pre_partials=self.pre_buffers(d))
             inst.load(d.tips, d.weights, d.V, d.Vinv, d.lam, d.pi, d.rates, d.cat_weights,
                       children=d.children)
         except BaseException:
             torch.cuda.synchronize(self.device)
-            self.memory.free(ptr)
+            self.arena.release(ptr, s.footprint)
             raise
         nb = 2 * d.n_tips - 2
         s.state = {"inst": inst, "ptr": ptr,
@@ -164,19 +233,23 @@ class HipExecutor:
 
     def evict(self, s):
         if s.state is not None:
+            # the session is idle: its last batch has completed and its uploads were
+            # synchronous, so nothing in flight reads this range any more
             s.state["inst"].close()
-            # work on the session has completed (it is idle), but its uploads ran on the
-            # instance's stream: let the device drain before the memory is reused
-            self.torch.cuda.synchronize(self.device)
-            self.memory.free(s.state["ptr"])
+            self.arena.release(s.state["ptr"], s.footprint)
         s.state = None
 
     def launch(self, key, items):
         """items: [(session, t)].  Enqueue one batched evaluation; return a completion token."""
         torch = self.torch
-        stream = self.streams.get(key)
-        if stream is None:
-            stream = self.streams[key] = torch.cuda.Stream(device=self.device)
+        # a few streams per class, in turn, so that a long batch does not hold up the next
+        # short one of the same class
+        pool = self.streams.get(key)
+        if pool is None:
+            pool = self.streams[key] = [torch.cuda.Stream(device=self.device)
+                                        for _ in range(self.STREAMS_PER_CLASS)]
+        stream = pool[self.turn[key] % len(pool)]
+        self.turn[key] += 1
         with torch.cuda.stream(stream):
             for s, t in items:
                 st = s.state
@@ -254,6 +327,8 @@ class Server:
         if memory_budget is None:
             memory_budget = int(0.85 * self.ex.free_memory())
         self.memory_budget = int(memory_budget)
+        if hasattr(self.ex, "reserve"):
+            self.ex.reserve(self.memory_budget)
         self.max_session_bytes = int(max_session_bytes or self.memory_budget // 4)
         self.max_batch = max(1, min(int(max_batch), MAX_BATCH))
         self.max_inflight = max(1, int(max_inflight_per_class))
@@ -273,6 +348,9 @@ class Server:
         self.batches = 0
         self.batch_sizes = []
         self.evictions = 0
+        self.loads = 0
+        self.load_seconds = 0.0
+        self.evict_seconds = 0.0
         self.max_concurrent_batches = 0
         self.t_first = None
         self.t_last = None
@@ -343,6 +421,8 @@ class Server:
                 if s.resident:
                     self.ex.evict(s)
         self.used = 0
+        if hasattr(self.ex, "close"):
+            self.ex.close()
 
     def __enter__(self):
         return self.start()
@@ -354,7 +434,8 @@ class Server:
         """Start a new measurement window (counters, latencies, throughput span)."""
         with self.cv:
             self.latencies = []
-            self.completed = self.errors = self.batches = self.evictions = 0
+            self.completed = self.errors = self.batches = self.evictions = self.loads = 0
+            self.load_seconds = self.evict_seconds = 0.0
             self.batch_sizes = []
             self.max_concurrent_batches = 0
             self.t_first = self.t_last = None
@@ -365,7 +446,8 @@ class Server:
         return {"completed": self.completed, "errors": self.errors, "batches": self.batches,
                 "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
                 "max_concurrent_batches": self.max_concurrent_batches,
-                "evictions": self.evictions,
+                "evictions": self.evictions, "loads": self.loads,
+                "load_seconds": self.load_seconds, "evict_seconds": self.evict_seconds,
                 "p50_ms": 1000 * float(np.percentile(lat, 50)),
                 "p99_ms": 1000 * float(np.percentile(lat, 99)),
                 "mean_ms": 1000 * float(np.mean(lat)),
@@ -410,35 +492,45 @@ class Server:
                     self._fail(req, err)
             self.inflight = []
 
+    def _idle_lru(self):
+        idle = [x for sess in self.sessions.values() for x in sess
+                if x.resident and not x.busy and not self.pending.get(x)]
+        return min(idle, key=lambda x: x.last_used) if idle else None
+
+    def _evict(self, x):
+        t0 = time.perf_counter()
+        self.ex.evict(x)
+        self.used -= x.footprint
+        self.evictions += 1
+        self.evict_seconds += time.perf_counter() - t0
+
     def _admit(self, s: _Session) -> bool:
+        """Make s resident: evict idle sessions, least recently used first, until its
+        footprint fits the budget and the executor finds room for it (a fragmented arena
+        can refuse a fitting total); False if that cannot be done now."""
         if s.resident:
             return True
-        if self.used + s.footprint > self.memory_budget:
-            idle = [x for sess in self.sessions.values() for x in sess
-                    if x.resident and not x.busy and not self.pending.get(x)]
-            idle.sort(key=lambda x: x.last_used)
-            need = self.used + s.footprint - self.memory_budget
-            victims, freed = [], 0
-            for x in idle:
-                if freed >= need:
-                    break
-                victims.append(x)
-                freed += x.footprint
-            if freed < need:
+        while True:
+            if self.used + s.footprint <= self.memory_budget:
+                t0 = time.perf_counter()
+                try:
+                    s.key = self.ex.load(s)
+                except MemoryError:
+                    pass                              # no contiguous room: evict more
+                except Exception as e:  # noqa: BLE001 - fail this session's requests only
+                    for req in self.pending.get(s, ()):
+                        self._fail(req, e)
+                    self.pending[s] = collections.deque()
+                    return False
+                else:
+                    self.used += s.footprint
+                    self.loads += 1
+                    self.load_seconds += time.perf_counter() - t0
+                    return True
+            victim = self._idle_lru()
+            if victim is None:
                 return False
-            for x in victims:
-                self.ex.evict(x)
-                self.used -= x.footprint
-                self.evictions += 1
-        try:
-            s.key = self.ex.load(s)
-        except Exception as e:  # noqa: BLE001 - fail this session's requests only
-            for req in self.pending.get(s, ()):
-                self._fail(req, e)
-            self.pending[s] = collections.deque()
-            return False
-        self.used += s.footprint
-        return True
+            self._evict(victim)
 
     def _dispatch(self) -> bool:
         launched = False
@@ -507,4 +599,4 @@ class Server:
         return done_any
 
 
-__all__ = ["Server", "Dataset", "HipExecutor"]
+__all__ = ["Server", "Dataset", "HipExecutor", "Arena"]

@@ -128,16 +128,30 @@ def test_plan_tree_orders_and_rescaling(lib, maker, period):
             run = 0 if resc[v] else run + 1
             assert run < period
             v = int(tree.parent[v])
-    # pre-order: parents before children, root first with parent_pre -1
+    # pre-order: parents before children, root first with parent_pre -1; buffers reused
+    # from a free list: every read finds its parent's partial, never overwritten before
     assert pre[0][0] == -1
+    n_buf = ctypes.c_int()
+    ch = np.ascontiguousarray(tree.children.astype(np.int32))
+    assert lib.hp_plan_pre_buffers(N, ctypes.c_void_p(ch.ctypes.data), ctypes.byref(n_buf)) == 0
     have = {tree.root}
+    holds = {}                                       # pre buffer -> node whose partial it holds
     for row in pre:
-        parent = tree.root if row[0] < 0 else row[0] + N
-        assert parent in have
+        parent = int(tree.parent[row[1]])
+        assert parent == int(tree.parent[row[5]]) and parent in have
+        if parent == tree.root:
+            assert row[0] == -1
+        else:
+            assert holds.get(int(row[0])) == parent
         for post_c, mat, pre_c, g in (row[1:5], row[5:9]):
             assert mat == post_c == g
-            assert pre_c == (post_c - N if post_c >= N else -1)
+            if post_c >= N:
+                assert 0 <= pre_c < n_buf.value and pre_c != row[0]
+                holds[int(pre_c)] = int(post_c)
+            else:
+                assert pre_c == -1
             have.add(int(post_c))
+        assert row[3] < 0 or row[3] != row[7]
     assert len(have) == 2 * N - 1
 
 
@@ -160,3 +174,33 @@ def test_plan_tree_rejects_non_trees(lib):
     ch = tree.children.copy()
     ch[6, 1] = 10                                          # the root as a child
     assert plan(lib, synth.Tree(6, tree.parent, ch))[0] in (_lib.HP_ERR_ARG, _lib.HP_ERR_INDEX)
+
+
+def _height(tree):
+    h = np.zeros(2 * tree.n_tips - 1, dtype=int)
+    for v in range(tree.n_tips, 2 * tree.n_tips - 1):          # children have smaller numbers
+        h[v] = 1 + max(h[c] for c in tree.children[v])
+    return int(h[tree.root])
+
+
+@pytest.mark.parametrize("maker,N", [("cat", 200), ("bal", 256), ("yule", 1000), ("yule", 5)])
+def test_pre_buffers_bounded_by_height(lib, maker, N):
+    tree = {"yule": synth.yule_tree(N, np.random.default_rng(N)), "cat": synth.caterpillar_tree(N),
+            "bal": synth.balanced_tree(N)}[maker]
+    n = _lib.plan_pre_buffers(tree.children)
+    assert 1 <= n <= _height(tree) + 1
+    if maker == "bal":
+        assert n <= int(np.log2(N)) + 1
+    if maker == "cat":
+        assert n <= 2
+    if maker == "yule" and N == 1000:
+        assert n < 60                                   # versus 999 without reuse
+
+
+def test_workspace_shrinks_with_pre_buffers(lib):
+    rc, full = ws_bytes(lib, desc())
+    rc2, small = ws_bytes(lib, desc(n_pre_partials=20))
+    assert rc == rc2 == 0
+    per_buffer = 4 * 100096 * 4 * 4        # K * P_pad * S_pad * FP32, P_pad a multiple of 128
+    assert abs((full - small) - (127 - 20) * per_buffer) < 2048
+    assert ws_bytes(lib, desc(n_pre_partials=-1))[0] == _lib.HP_ERR_ARG

@@ -325,3 +325,22 @@ def test_error_codes():
         inst.status()
     assert e.value.code == _lib.HP_ERR_VALUE
     inst.status()                                               # cleared
+
+
+@pytest.mark.parametrize("kind,n,npat,precision", [("gtr", 300, 700, "f32"), ("gtr", 64, 2000, "f64"),
+                                                   ("gy94", 40, 300, "bf16"), ("aa", 90, 500, "f32")])
+def test_minimal_pre_buffers_bitwise_equal(kind, n, npat, precision):
+    """Whole-tree instances sized with hp_plan_pre_buffers (buffers reused along the pre-order
+    walk) give exactly the results of instances with one pre-order buffer per node."""
+    from paper_2606_27607_amd import _lib
+    wl = synth.make_workload(kind, n, npat, seed=n, unknown_frac=0.05)
+    need = _lib.plan_pre_buffers(wl.tree.children)
+    assert need < n // 3
+    sc = ("every_k", 4) if wl.n_states <= 4 else ("every_node", 1)
+    full = make_instance(wl, precision, *sc)
+    small = make_instance(wl, precision, *sc, n_pre_partials=need)
+    assert small.workspace_bytes < full.workspace_bytes
+    a, b = full.evaluate(wl.t), small.evaluate(wl.t)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+    with pytest.raises(Exception):
+        make_instance(wl, precision, *sc, n_pre_partials=need - 1)

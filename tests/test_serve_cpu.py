@@ -8,17 +8,18 @@ import numpy as np
 import pytest
 
 from paper_2606_27607_amd import _lib
-from paper_2606_27607_amd.serve import Dataset, Server
+from paper_2606_27607_amd.serve import Arena, Dataset, Server
 
 
 class FakeExecutor:
     def __init__(self, service_s=0.002, fail_clients=(), raise_on_launch=(), raise_on_load=(),
-                 raise_on_poll=0):
+                 raise_on_poll=0, arena_bytes=None):
         self.service_s = service_s
         self.fail_clients = set(fail_clients)
         self.raise_on_launch = set(raise_on_launch)
         self.raise_on_load = set(raise_on_load)
         self.raise_on_poll = raise_on_poll            # polls that raise, counted down
+        self.arena = Arena(1 << 40, arena_bytes) if arena_bytes else None
         self.resident = set()
         self.used = 0
         self.budget = None
@@ -34,16 +35,19 @@ class FakeExecutor:
 
     def load(self, s):
         if s.client in self.raise_on_load:
-            raise MemoryError("device allocation failed")
+            raise RuntimeError("device allocation failed")
+        ptr = self.arena.alloc(s.footprint) if self.arena else None
         with self.lock:
             assert s not in self.resident
             self.resident.add(s)
             self.used += s.footprint
             self.max_used = max(self.max_used, self.used)
-        s.state = {"loaded": True}
+        s.state = {"loaded": True, "ptr": ptr}
         return (s.precision, 4 if s.data.n_states <= 4 else 64, len(s.data.rates))
 
     def evict(self, s):
+        if self.arena:
+            self.arena.release(s.state["ptr"], s.footprint)
         with self.lock:
             self.resident.discard(s)
             self.used -= s.footprint
@@ -196,11 +200,11 @@ def test_load_failure_fails_only_that_session():
         for c in range(4):
             srv.register(c, dataset(5, 30))
         futs = {c: srv.submit(c, np.full(8, 0.1)) for c in range(4)}
-        with pytest.raises(MemoryError):
+        with pytest.raises(RuntimeError):
             futs[2].result(timeout=10)
         for c in (0, 1, 3):
             assert futs[c].result(timeout=10)[0] == pytest.approx(0.8 * 30)
-        with pytest.raises(MemoryError):                 # still failing, still isolated
+        with pytest.raises(RuntimeError):                # still failing, still isolated
             srv.evaluate(2, np.full(8, 0.1))
         assert srv.evaluate(1, np.full(8, 0.2))[0] == pytest.approx(1.6 * 30)
 
@@ -217,3 +221,38 @@ def test_loop_survives_unexpected_errors():
             with pytest.raises(RuntimeError):
                 f.result(timeout=10)
         assert srv.evaluate(0, np.full(8, 0.1))[0] == pytest.approx(0.8 * 30)
+
+
+def test_arena_first_fit_and_coalescing():
+    a = Arena(4096, 256 * 100)
+    p = [a.alloc(256 * n) for n in (10, 20, 30, 40)]
+    assert p == [4096, 4096 + 2560, 4096 + 7680, 4096 + 15360]
+    with pytest.raises(MemoryError):
+        a.alloc(256 * 1)                                  # full
+    a.release(p[1], 256 * 20)
+    a.release(p[2], 256 * 30)                             # coalesces with p[1]'s range
+    assert a.largest() == 256 * 50
+    assert a.alloc(256 * 45) == p[1]
+    a.release(p[0], 256 * 10)
+    a.release(p[1], 256 * 45)
+    a.release(p[3], 256 * 40)
+    assert a.free == [(0, 256 * 100)]
+    assert a.alloc(100) == 4096                           # rounded up to a granule
+    assert a.largest() == 256 * 99
+
+
+def test_fragmented_memory_evicts_until_a_range_fits():
+    """Sessions sized 3, 3, 3 (budget 10): a size-4 session fits the budget after one
+    eviction but needs two neighbouring ranges free, so admission evicts more."""
+    unit = 5 * 100 * 8
+    ex = FakeExecutor(service_s=0.001, arena_bytes=10 * unit)
+    with Server(memory_budget=10 * unit, executor=ex) as srv:
+        for c in range(3):
+            srv.register(c, dataset(5, 300))              # footprint 3 units each
+        srv.register(3, dataset(5, 400))                  # 4 units
+        for c in range(3):
+            srv.evaluate(c, np.full(8, 0.1))
+        srv.evaluate(1, np.full(8, 0.1))                  # client 0 is now least recently used
+        assert srv.evaluate(3, np.full(8, 0.1))[0] == pytest.approx(0.8 * 400)
+        st = srv.stats()
+    assert st["evictions"] >= 2 and ex.max_used <= 10 * unit
