@@ -192,8 +192,8 @@ def measure(wl, precision: str, steps: int, warmup: int, latency_samples: int) -
 
 
 def measure_rate_gradient(wl, precision: str, steps: int, warmup: int) -> dict:
-    """lnL + branch gradients + the first-order rate-matrix gradient per evaluation (4-state
-    path): throughput, traversal time against the plain evaluation's, error vs the oracle."""
+    """lnL + branch gradients + the first-order rate-matrix gradient per evaluation:
+    throughput, traversal time against the plain evaluation's, error vs the oracle."""
     import numpy as np
     import torch
 
@@ -201,8 +201,11 @@ def measure_rate_gradient(wl, precision: str, steps: int, warmup: int) -> dict:
 
     N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
     nb = 2 * N - 2
-    inst = Instance(N, P, S, K, precision=precision, scaling="every_k",
-                    scale_period=max(1, wl.meta.get("scale_every", 4)))
+    if S <= 4:
+        inst = Instance(N, P, S, K, precision=precision, scaling="every_k",
+                        scale_period=max(1, wl.meta.get("scale_every", 4)))
+    else:
+        inst = Instance(N, P, S, K, precision=precision, scaling="every_node")
     inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
               children=wl.tree.children)
     rng = np.random.default_rng(2)
@@ -486,9 +489,11 @@ def main():
                     "lnl_rel_err": by[(64, p)]["error_vs_oracle"].get("lnl_rel")}
                 for p in ("bf16", "f16") if (64, p) in by}
         print("[bench] rate-matrix gradient", file=sys.stderr, flush=True)
-        line["rate_matrix_gradient"] = [measure_rate_gradient(synth.config_workload("nuc128"), p,
-                                                              max(10, args.steps // 2), 3)
-                                        for p in ("f32", "f64")]
+        line["rate_matrix_gradient"] = (
+            [measure_rate_gradient(synth.config_workload("nuc128"), p, max(10, args.steps // 2), 3)
+             for p in ("f32", "f64")]
+            + [measure_rate_gradient(wls.get("codon64") or synth.config_workload("codon64"), p,
+                                     max(10, args.steps // 4), 3) for p in ("f32", "bf16")])
         print("[bench] autograd modes", file=sys.stderr, flush=True)
         line["autograd"] = [measure_autograd(synth.config_workload("nuc256"), "f32", 20),
                             measure_autograd(synth.config_workload("codon32"), "bf16", 20)]

@@ -253,7 +253,8 @@ int hp_gradients_device(hp_instance* inst, double* d_grad);
  * the chain rule to its model's parameters (and to the rate normalisation, if any).
  * One whole-tree evaluation as hp_evaluate with want_grad = 1, plus G: out_lnl (1),
  * out_grad (2N-2, by node) and out_rate_grad (S*S, row-major), host pointers, blocking.
- * n_states <= 4 only (HP_ERR_UNSUPPORTED otherwise). */
+ * For n_states > 4 the products that form G run on the matrix cores (BF16 operands on the
+ * BF16/FP16 paths); FP64 with n_states > 32 and n_categories > 4 is HP_ERR_UNSUPPORTED. */
 int hp_evaluate_rate_gradient(hp_instance* inst, const double* t, double* out_lnl, double* out_grad,
                               double* out_rate_grad);
 /* The same, stream-ordered on device pointers: d_t (2N-2 FP64) and d_out (1 + 2N-2 + S*S FP64:

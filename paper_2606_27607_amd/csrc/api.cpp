@@ -114,8 +114,8 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     l.mat_stride = (size_t)K * S_pad * S_pad;
     l.tip_stride = (size_t)K * (S + 1) * S_pad;
     l.eig_stride = (size_t)2 * S * S + S;
-    // lnL, the branch gradients and, on the 4-state path, the rate-matrix gradient
-    l.max_out = 1 + max_grad_slots(d) + (S_pad == 4 ? kQSlots : 0);
+    // lnL, the branch gradients and the rate-matrix gradient
+    l.max_out = 1 + max_grad_slots(d) + (S_pad == 4 ? kQSlots : S_pad * S_pad);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -907,12 +907,20 @@ int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, doub
     return enqueue_evaluate(I, d_t, want_grad, d_out);
 }
 
+// The matrix-core kernel stages the rate-gradient products in LDS; FP64 with 64 padded states
+// and more than 4 categories would need more than a workgroup has.
+static bool rate_gradient_supported(const Instance* I) {
+    return !(I->d.precision == HP_PREC_F64 && I->S_pad == 64 && I->d.n_categories > 4);
+}
+static const char* const kRateGradUnsupported =
+    "the rate-matrix gradient in FP64 with more than 32 states supports at most 4 categories";
+
 int hp_evaluate_rate_gradient(hp_instance* inst, const double* t, double* out_lnl, double* out_grad,
                               double* out_rate_grad) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
     if (!t || !out_lnl || !out_grad || !out_rate_grad) return fail(I, HP_ERR_ARG, "NULL argument");
-    if (I->S_pad != 4) return fail(I, HP_ERR_UNSUPPORTED, "the rate-matrix gradient needs n_states <= 4");
+    if (!rate_gradient_supported(I)) return fail(I, HP_ERR_UNSUPPORTED, kRateGradUnsupported);
     int rc = check_eval_state(I);
     if (rc) return rc;
     const int nb = 2 * I->d.n_tips - 2, S = I->d.n_states;
@@ -944,7 +952,7 @@ int hp_evaluate_rate_gradient_device(hp_instance* inst, const double* d_t, doubl
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
     if (!d_t || !d_out) return fail(I, HP_ERR_ARG, "NULL argument");
-    if (I->S_pad != 4) return fail(I, HP_ERR_UNSUPPORTED, "the rate-matrix gradient needs n_states <= 4");
+    if (!rate_gradient_supported(I)) return fail(I, HP_ERR_UNSUPPORTED, kRateGradUnsupported);
     int rc = check_eval_state(I);
     if (rc) return rc;
     DeviceGuard g(I->d.device);
