@@ -52,12 +52,15 @@ struct DeviceGuard {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+const char* const kEigWholeTreeOnly =
+    "more than 64 states: only whole-tree evaluation (hp_set_tree, hp_evaluate[_device]) is supported";
+
 int check_desc(const hp_desc* d) {
     if (!d) return fail(nullptr, HP_ERR_ARG, "descriptor is NULL");
     if (d->n_tips < 2) return fail(nullptr, HP_ERR_ARG, "n_tips must be >= 2");
     if (d->n_patterns < 1) return fail(nullptr, HP_ERR_ARG, "n_patterns must be >= 1");
-    if (d->n_states < 2 || d->n_states > hp::kMaxStates)
-        return fail(nullptr, HP_ERR_UNSUPPORTED, "n_states must be in [2, 64]");
+    if (d->n_states < 2 || d->n_states > hp::kMaxStatesEig)
+        return fail(nullptr, HP_ERR_UNSUPPORTED, "n_states must be in [2, 254]");
     if (d->n_categories < 1 || d->n_categories > hp::kMaxCategories)
         return fail(nullptr, HP_ERR_UNSUPPORTED, "n_categories must be in [1, 8]");
     if (d->n_partials < 1 || d->n_matrices < 1 || d->n_eigen < 1)
@@ -73,6 +76,8 @@ int check_desc(const hp_desc* d) {
     if (lowp && d->n_states <= 4)
         return fail(nullptr, HP_ERR_UNSUPPORTED,
                     "BF16/FP16 matrix-core partials are for S > 4 (amino-acid and codon models)");
+    if (lowp && d->n_states > hp::kMaxStates)
+        return fail(nullptr, HP_ERR_UNSUPPORTED, "more than 64 states run in FP64 or FP32");
     // guard the int32 index arithmetic inside kernels
     const double pad_p = std::ceil(d->n_patterns / 64.0) * 64.0;
     if (pad_p * d->n_categories * 64.0 > 2.0e9)
@@ -92,7 +97,63 @@ int n_pre(const hp_desc& d) { return d.n_pre_partials > 0 ? d.n_pre_partials : d
 
 namespace hp {
 
+// Layout of the eigensystem path (64 < S): no transition matrices; per-branch vectors.
+int compute_layout_eig(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_out, Layout* L) {
+    const int S = d.n_states, K = d.n_categories, N = d.n_tips, P = d.n_patterns;
+    const int S_pad = (S + 15) / 16 * 16;
+    const int elem = d.precision == HP_PREC_F64 ? 8 : 4;
+    const size_t nbr = (size_t)2 * N - 2;
+    const size_t np = (size_t)std::max(d.n_partials, N - 1);
+    const size_t ne = (size_t)d.n_eigen;
+    Layout l{};
+    l.tile = 1;
+    l.n_blocks = P;                                    // reduction rows hold one column per pattern
+    l.post_stride = (size_t)K * P * S_pad;
+    l.mat_stride = 0;
+    l.tip_stride = 0;
+    l.eig_stride = (size_t)2 * S * S + S;
+    l.max_out = 1 + max_grad_slots(d);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    l.tips = take((size_t)N * P);
+    l.pweights = take((size_t)P * 8);
+    l.post = take(np * l.post_stride * elem);          // x of internal nodes
+    l.post_exp = take(np * P * 4);
+    l.pre = take(np * l.post_stride * elem);           // q of internal nodes
+    l.eig_U = take(nbr * l.post_stride * elem);
+    l.eig_Y = take(nbr * l.post_stride * elem);
+    l.eig_Z = take(nbr * l.post_stride * elem);
+    l.eig_W = take(nbr * l.post_stride * elem);
+    l.eig_E = take(nbr * K * S_pad * elem);
+    l.eig = take(ne * l.eig_stride * 8);
+    l.eig_V = take((size_t)4 * S_pad * S_pad * elem);
+    l.eig_lam = take((size_t)S_pad * 8);
+    l.Qc = take(ne * S_pad * S_pad * elem);
+    l.freq_c = take(ne * S_pad * elem);
+    l.freq_d = take(ne * S_pad * 8);
+    l.cat_d = take(2 * kMaxCategories * 8);
+    l.t_stage = take(nbr * 8);
+    l.idx_stage = take(nbr * 4);
+    l.eig_lists = take((size_t)6 * N * 4);
+    l.eig_children = take((size_t)(2 * N - 1) * 2 * 4);
+    l.partials = take((size_t)l.max_out * P * 8);
+    l.results = take((size_t)l.max_out * 8);
+    l.status = take(64);
+    l.site = take((size_t)P * 8);
+    l.total = off;
+    *S_pad_out = S_pad;
+    *P_pad_out = P;
+    *elem_out = elem;
+    *L = l;
+    return HP_OK;
+}
+
 int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_out, Layout* L) {
+    if (d.n_states > kMaxStates) return compute_layout_eig(d, S_pad_out, P_pad_out, elem_out, L);
     const int S = d.n_states, K = d.n_categories;
     const bool lowp = d.precision == HP_PREC_BF16 || d.precision == HP_PREC_F16;
     int S_pad;
@@ -343,8 +404,9 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
         return fail(nullptr, HP_ERR_WORKSPACE, "workspace smaller than hp_workspace_bytes");
     }
     I->n_blocks = I->L.n_blocks;
+    I->eig = desc->n_states > hp::kMaxStates;
     if (I->S_pad == 4) choose_small_tile(I);
-    else choose_mfma_blocks(I);
+    else if (!I->eig) choose_mfma_blocks(I);
     I->ws = static_cast<uint8_t*>(dev_workspace);
     I->ws_bytes = workspace_bytes;
     I->stream = static_cast<hipStream_t>(hip_stream);
@@ -520,6 +582,23 @@ int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv
     if (rc) return rc;
     rc = upload_compute(I, I->L.Qc + (size_t)idx * Sp * Sp * (I->d.precision == HP_PREC_F64 ? 8 : 4), Q);
     if (rc) return rc;
+    if (I->eig && idx == 0) {
+        // V, V^-1, V^T, V^-T zero-padded to S_pad, in the compute type, and lambda (FP64)
+        const size_t msz = (size_t)Sp * Sp;
+        std::vector<double> M(4 * msz, 0.0), lp(Sp, 0.0);
+        for (int x = 0; x < S; ++x)
+            for (int y = 0; y < S; ++y) {
+                M[(size_t)x * Sp + y] = V[x * S + y];
+                M[msz + (size_t)x * Sp + y] = Vinv[x * S + y];
+                M[2 * msz + (size_t)y * Sp + x] = V[x * S + y];
+                M[3 * msz + (size_t)y * Sp + x] = Vinv[x * S + y];
+            }
+        std::copy(lam, lam + S, lp.begin());
+        rc = upload_compute(I, I->L.eig_V, M);
+        if (rc) return rc;
+        rc = upload(I, I->ws + I->L.eig_lam, lp.data(), lp.size() * 8);
+        if (rc) return rc;
+    }
     if (I->L.Q16) {
         // hi part, then (BF16) the lo part Q - hi, so that a matrix product with Q in two
         // 16-bit MFMAs carries ~2^-17 relative error in Q instead of 2^-9
@@ -546,6 +625,7 @@ int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv
 int hp_update_matrices(hp_instance* inst, int eigen_idx, const int32_t* mat_idx, const double* t, int count) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
     if (count < 0 || count > I->d.n_matrices) return fail(I, HP_ERR_ARG, "bad matrix count");
     if (count == 0) return HP_OK;
     if (!mat_idx || !t) return fail(I, HP_ERR_ARG, "mat_idx or t is NULL");
@@ -568,6 +648,7 @@ int hp_update_matrices(hp_instance* inst, int eigen_idx, const int32_t* mat_idx,
 int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
     if (count < 0 || count > max_ops(I->d)) return fail(I, HP_ERR_ARG, "bad operation count");
     if (count == 0) return HP_OK;
     if (!ops) return fail(I, HP_ERR_ARG, "ops is NULL");
@@ -595,6 +676,7 @@ int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count) {
 int hp_root_lnl(hp_instance* inst, int root_buf, int freq_idx, double* out_lnl, double* out_site) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
     if (!out_lnl) return fail(I, HP_ERR_ARG, "out_lnl is NULL");
     int rc = check_post_buf(I, root_buf, "root_buf");
     if (rc) return rc;
@@ -653,6 +735,7 @@ static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_
                    double* out_grad, int n_grad, bool grad) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
     if (count < 0 || count > max_ops(I->d)) return fail(I, HP_ERR_ARG, "bad operation count");
     if (count > 0 && !ops) return fail(I, HP_ERR_ARG, "ops is NULL");
     if (freq_idx < 0 || freq_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "frequency slot out of range");
@@ -803,10 +886,75 @@ int hp_plan_pre_buffers(int n_tips, const int32_t* children, int* out_count) {
     return plan_tree(nullptr, n_tips, children, HP_SCALE_NONE, 1, &post, &pre, out_count);
 }
 
+// Level schedule of the eigensystem path from a validated children table: post-order levels
+// by height (internal nodes; the root alone is last) and pre-order levels by depth.
+static int set_tree_eig(Instance* I, const int32_t* children) {
+    const int N = I->d.n_tips, n_nodes = 2 * N - 1, root = 2 * N - 2;
+    std::vector<int32_t> post, pre;
+    int rc = plan_tree(I, N, children, HP_SCALE_NONE, 1, &post, &pre);   // validates the table
+    if (rc) return rc;
+    std::vector<int> height(n_nodes, 0), depth(n_nodes, 0), parent(n_nodes, -1);
+    for (size_t i = 0; i < post.size(); i += hp::kPostOpInts) {          // children first
+        const int v = post[i], a = post[i + 1], b = post[i + 3];
+        height[v] = 1 + std::max(height[a], height[b]);
+    }
+    for (int v = N; v < n_nodes; ++v) parent[children[2 * v]] = parent[children[2 * v + 1]] = v;
+    for (size_t i = 0; i < pre.size(); i += hp::kPreOpInts) {            // parents first
+        const int a = pre[i + 1], b = pre[i + 5];
+        depth[a] = depth[b] = depth[parent[a]] + 1;
+    }
+    const int H = height[root];
+    int D = 0;
+    for (int v = N; v < n_nodes; ++v) D = std::max(D, depth[v]);
+    std::vector<int32_t> lists;
+    hp::EigPlan plan;
+    plan.tips_off = 0;
+    for (int v = 0; v < N; ++v) lists.push_back(v);
+    std::vector<std::vector<int>> by_h(H + 1), by_d(D + 1);
+    for (int v = N; v < n_nodes; ++v) {
+        by_h[height[v]].push_back(v);
+        by_d[depth[v]].push_back(v);
+    }
+    for (int h = 1; h <= H; ++h) {
+        if (by_h[h].empty()) continue;
+        const bool is_root = h == H;
+        plan.post.push_back({(int)lists.size(), (int)by_h[h].size(), is_root});
+        lists.insert(lists.end(), by_h[h].begin(), by_h[h].end());
+    }
+    for (int d = 0; d <= D; ++d) {
+        if (by_d[d].empty()) continue;
+        hp::EigPreLevel lv{};
+        lv.off = (int)lists.size();
+        lv.n = (int)by_d[d].size();
+        lists.insert(lists.end(), by_d[d].begin(), by_d[d].end());
+        lv.kids_off = (int)lists.size();
+        for (int v : by_d[d]) lists.insert(lists.end(), {children[2 * v], children[2 * v + 1]});
+        lv.n_kids = 2 * lv.n;
+        lv.inner_off = (int)lists.size();
+        for (int v : by_d[d])
+            for (int c : {children[2 * v], children[2 * v + 1]})
+                if (c >= N) lists.push_back(c);
+        lv.n_inner = (int)lists.size() - lv.inner_off;
+        plan.pre.push_back(lv);
+    }
+    if (lists.size() > (size_t)6 * N) return fail(I, HP_ERR_DEVICE, "level lists exceed their region");
+    DeviceGuard g(I->d.device);
+    rc = upload(I, I->ws + I->L.eig_lists, lists.data(), lists.size() * 4);
+    if (rc) return rc;
+    rc = upload(I, I->ws + I->L.eig_children, children, (size_t)n_nodes * 2 * 4);
+    if (rc) return rc;
+    I->eig_plan = std::move(plan);
+    I->tree_set = true;
+    I->tree_n_post = N - 1;
+    I->tree_n_pre = N - 1;
+    return HP_OK;
+}
+
 int hp_set_tree(hp_instance* inst, const int32_t* children) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
     if (!children) return fail(I, HP_ERR_ARG, "children is NULL");
+    if (I->eig) return set_tree_eig(I, children);
     const int N = I->d.n_tips;
     if (I->d.n_partials < N - 1) return fail(I, HP_ERR_ARG, "n_partials < n_tips - 1");
     if (I->d.n_matrices < 2 * N - 2) return fail(I, HP_ERR_ARG, "n_matrices < 2 n_tips - 2");
@@ -841,6 +989,11 @@ int hp_set_tree(hp_instance* inst, const int32_t* children) {
 static int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out,
                             bool rate_grad = false) {
     const int N = I->d.n_tips;
+    if (I->eig) {
+        HP_HIP(I, timed(I, hp::kTraversal, [&] { return hp::launch_eig_evaluate(*I, d_t, want_grad, d_out); }));
+        HP_HIP(I, HP_REDUCE(*I, want_grad ? 2 * N - 1 : 1, d_out));
+        return HP_OK;
+    }
     HP_HIP(I, HP_PMAT(*I, 0, nullptr, d_t, 2 * N - 2));
     hp::WalkArgs a;
     a.mode = want_grad ? (hp::kPost | hp::kRootFused | hp::kPre | hp::kGrad) : (hp::kPost | hp::kRootFused);
@@ -919,6 +1072,7 @@ int hp_evaluate_rate_gradient(hp_instance* inst, const double* t, double* out_ln
                               double* out_rate_grad) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
     if (!t || !out_lnl || !out_grad || !out_rate_grad) return fail(I, HP_ERR_ARG, "NULL argument");
     if (!rate_gradient_supported(I)) return fail(I, HP_ERR_UNSUPPORTED, kRateGradUnsupported);
     int rc = check_eval_state(I);
@@ -951,6 +1105,7 @@ int hp_evaluate_rate_gradient(hp_instance* inst, const double* t, double* out_ln
 int hp_evaluate_rate_gradient_device(hp_instance* inst, const double* d_t, double* d_out) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
     if (!d_t || !d_out) return fail(I, HP_ERR_ARG, "NULL argument");
     if (!rate_gradient_supported(I)) return fail(I, HP_ERR_UNSUPPORTED, kRateGradUnsupported);
     int rc = check_eval_state(I);
@@ -972,6 +1127,7 @@ int hp_batch_evaluate_device(hp_instance* const* insts, const double* const* d_t
     for (int i = 0; i < n; ++i) {
         Instance* I = reinterpret_cast<Instance*>(insts[i]);
         if (!I || !d_t[i] || !d_out[i]) return fail(nullptr, HP_ERR_ARG, "NULL instance or pointer in batch");
+        if (I->eig) return fail(nullptr, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
         for (int j = 0; j < i; ++j)
             if (insts[j] == insts[i]) return fail(nullptr, HP_ERR_ARG, "an instance appears twice in one batch");
         if (I->d.device != first->d.device || I->d.precision != first->d.precision ||
@@ -1041,6 +1197,7 @@ int hp_profile_read(hp_instance* inst, double* out_ms, int64_t* out_count) {
 int hp_gradients_device(hp_instance* inst, double* d_grad) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
     if (!d_grad) return fail(I, HP_ERR_ARG, "NULL argument");
     int rc = check_eval_state(I);
     if (rc) return rc;

@@ -14,7 +14,8 @@ namespace hp {
 
 constexpr int kWave = 64;          // CDNA wavefront width: one lane per pattern
 constexpr int kMaxCategories = 8;
-constexpr int kMaxStates = 64;
+constexpr int kMaxStates = 64;      // tiled paths (S <= 64)
+constexpr int kMaxStatesEig = 254;  // eigensystem path (64 < S), tip codes stay 8-bit
 constexpr int kPostOpInts = 6;     // hp_post_op
 constexpr int kPreOpInts = 9;      // hp_pre_op
 constexpr int kMfmaTile = 16;      // patterns per matrix-core tile
@@ -43,6 +44,10 @@ struct Layout {
     // matrix-core path only: P^T in the compute type, and 16-bit P, P^T and Q operands
     size_t matsT = 0, mats16 = 0, matsT16 = 0, Q16 = 0;
     size_t desc = 0;      // whole-tree descriptors: traversal with and without gradients, matrices
+    // eigensystem path (S > 64): per-branch vectors [branch][K][P][S_pad], e factors
+    // [branch][K][S_pad], V / V^-1 / V^T / V^-T and lambda of slot 0, level lists, children
+    size_t eig_E = 0, eig_U = 0, eig_Y = 0, eig_Z = 0, eig_W = 0, eig_V = 0, eig_lam = 0;
+    size_t eig_lists = 0, eig_children = 0;
     size_t post_stride;   // elements per partial buffer (K * P_pad * S_pad)
     size_t mat_stride;    // elements per matrix slot (K * S_pad * S_pad)
     size_t tip_stride;    // elements per tip-table slot (K * (S+1) * S_pad)
@@ -124,8 +129,25 @@ struct Profiler {
     int64_t count[kNumClasses] = {};
 };
 
+// Level schedule of the eigensystem path: post-order levels by height (node lists; the last
+// is the root) and pre-order levels by depth (nodes, their children, the internal children).
+struct EigPostLevel {
+    int off, n;
+    bool root;
+};
+struct EigPreLevel {
+    int off, n, kids_off, n_kids, inner_off, n_inner;
+};
+struct EigPlan {
+    int tips_off = 0;
+    std::vector<EigPostLevel> post;
+    std::vector<EigPreLevel> pre;
+};
+
 struct Instance {
     hp_desc d{};
+    bool eig = false;               // 64 < S: transition matrices applied through the eigensystem
+    EigPlan eig_plan;
     int S_pad = 0, P_pad = 0, elem = 0, n_blocks = 0;
     hipStream_t stream = nullptr;
     uint8_t* ws = nullptr;
@@ -192,6 +214,8 @@ hipError_t launch_walk(const Instance& I, const WalkArgs& a);
 size_t build_tree_desc(const Instance& I, int want_grad, void* host_buf);
 PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx);
 hipError_t launch_batch(const Instance& first, const BatchArgs& b, int want_grad);
+// Whole-tree evaluation on the eigensystem path (everything but the final pattern reduction).
+hipError_t launch_eig_evaluate(const Instance& I, const double* d_t, int want_grad, double* d_out);
 // Workgroups of the 4-state whole-tree kernel one CU holds with `ppl` patterns per lane.
 int small_blocks_per_cu(const Instance& I, int ppl);
 // Pattern tiles per wave of the matrix-core whole-tree kernel and its workgroups per CU.

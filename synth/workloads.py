@@ -85,6 +85,14 @@ def _model(kind: str, rng: np.random.Generator, **kw):
         f = [rng.dirichlet(np.full(4, 10.0)) for _ in range(3)]
         pi = models.f3x4(*f)
         return models.gy94(kw.get("kappa", 2.0), kw.get("omega", 0.3), pi), pi
+    if kind == "geo":
+        # discrete-location (phylogeography) model: S locations, exchangeability between
+        # every pair ~ Gamma(1, 1), location frequencies ~ Dir(1^S)
+        S = int(kw.get("n_states", 100))
+        pi = rng.dirichlet(np.ones(S))
+        R = np.zeros((S, S))
+        R[np.triu_indices(S, 1)] = rng.gamma(1.0, 1.0, size=S * (S - 1) // 2)
+        return models.reversible(R + R.T, pi), pi
     raise ValueError(f"unknown model kind {kind!r}")
 
 

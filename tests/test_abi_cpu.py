@@ -70,7 +70,7 @@ def test_workspace_sizing(lib):
 
 @pytest.mark.parametrize("field,value,code", [
     ("n_tips", 1, _lib.HP_ERR_ARG), ("n_patterns", 0, _lib.HP_ERR_ARG),
-    ("n_states", 65, _lib.HP_ERR_UNSUPPORTED), ("n_states", 1, _lib.HP_ERR_UNSUPPORTED),
+    ("n_states", 255, _lib.HP_ERR_UNSUPPORTED), ("n_states", 1, _lib.HP_ERR_UNSUPPORTED),
     ("n_categories", 9, _lib.HP_ERR_UNSUPPORTED), ("precision", 7, _lib.HP_ERR_ARG),
     ("scaling", 5, _lib.HP_ERR_ARG), ("scale_period", 0, _lib.HP_ERR_ARG),
     ("n_matrices", 0, _lib.HP_ERR_ARG),
@@ -204,3 +204,15 @@ def test_workspace_shrinks_with_pre_buffers(lib):
     per_buffer = 4 * 100096 * 4 * 4        # K * P_pad * S_pad * FP32, P_pad a multiple of 128
     assert abs((full - small) - (127 - 20) * per_buffer) < 2048
     assert ws_bytes(lib, desc(n_pre_partials=-1))[0] == _lib.HP_ERR_ARG
+
+
+def test_large_state_spaces_fp64_fp32_only(lib):
+    """More than 64 states (up to 254, tip codes stay 8-bit) run on the eigensystem path in
+    FP64 or FP32; its workspace holds per-branch vectors, not transition matrices."""
+    for prec in (0, 1):
+        rc, n = ws_bytes(lib, desc(n_states=200, n_patterns=3, n_tips=50, n_partials=49, n_matrices=98,
+                                   precision=prec))
+        assert rc == 0
+        vec = 98 * 4 * 3 * 208 * (8 if prec == 0 else 4)      # one per-branch vector array
+        assert 4 * vec < n < 12 * vec
+    assert ws_bytes(lib, desc(n_states=200, precision=2))[0] == _lib.HP_ERR_UNSUPPORTED
