@@ -256,6 +256,74 @@ def measure_rate_gradient(wl, precision: str, steps: int, warmup: int) -> dict:
             "error_vs_oracle": err}
 
 
+def eig_flops(n_tips: int, n_patterns: int, n_states: int, n_cat: int) -> float:
+    """Flops of one evaluation on the eigensystem path: every product is an S x S matrix
+    (V, V^-1, V^T or V^-T) times one vector per (node, category, pattern): u of every branch
+    (N tips + N-2 internal: V), y of every internal non-root node (V^-1), z of every branch
+    (V^T) and q of every internal non-root node (V^-T); S counted, not S_pad."""
+    vectors = (n_tips + (n_tips - 2) + (n_tips - 2) + (2 * n_tips - 2) + (n_tips - 2)) * n_cat * n_patterns
+    return vectors * 2.0 * n_states ** 2
+
+
+def measure_eig(wl, precision: str, steps: int, warmup: int) -> dict:
+    """The phylogeography-shaped workload on the eigensystem path (transition matrices applied
+    through V, V^-1 on the fly, never formed): throughput, traversal time, matrix-core rate,
+    error vs the stored oracle result, and what forming every P(t) alone would cost."""
+    import numpy as np
+    import torch
+
+    from paper_2606_27607_amd import Instance
+
+    N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
+    nb = 2 * N - 2
+    inst = Instance(N, P, S, K, precision=precision, scaling="every_node")
+    inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
+              children=wl.tree.children)
+    lnl, g = inst.evaluate(wl.t)
+    err = {}
+    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{wl.name}.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+        gg = np.array(gold["grad"])
+        err = {"lnl_rel": abs(lnl - gold["lnl"]) / abs(gold["lnl"]),
+               "grad_maxabs_over_maxabs": float(np.max(np.abs(g - gg)) / np.max(np.abs(gg))),
+               "reference": "FP64 oracle (scipy expm), full workload"}
+    rng = np.random.default_rng(3)
+    n_sets = steps + warmup
+    t_dev = torch.tensor(wl.t[:nb][None, :] * np.exp(0.05 * rng.standard_normal((n_sets, nb))),
+                         dtype=torch.float64, device=inst.device)
+    out = torch.empty((n_sets, 1 + nb), dtype=torch.float64, device=inst.device)
+    for i in range(warmup):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, n_sets):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    inst.profile(True)
+    inst.profile_read()
+    for i in range(warmup, n_sets):
+        inst.evaluate_device(t_dev[i], out=out[i])
+    prof = inst.profile_read()
+    inst.profile(False)
+    inst.status()
+    inst.close()
+    trav = prof["traversal"][0] / max(1, prof["traversal"][1])
+    fl = eig_flops(N, P, S, K)
+    form_p = nb * K * 2.0 * S ** 3
+    peak = MFMA_PEAK_TFLOPS[precision]
+    return {"workload": f"{wl.name}: {N}-taxon Yule tree, {S} locations (random reversible rates), "
+                        f"{P} pattern, {K} gamma categories, lnL + all {nb} branch gradients",
+            "precision": precision, "evals_per_s": 1000.0 / ms, "ms_per_eval": ms,
+            "traversal_ms": trav, "algorithmic_flops": fl,
+            "mfma_TFLOPs": fl / (trav * 1e-3) / 1e12, "mfma_frac": fl / (trav * 1e-3) / 1e12 / peak,
+            "forming_every_P_flops": form_p,
+            "forming_every_P_ms_at_peak": form_p / (peak * 1e12) * 1e3,
+            "error_vs_oracle": err}
+
+
 def measure_autograd(wl, precision: str, steps: int) -> dict:
     """Forward + backward of BranchLengthLnL per mode (store / recompute / fused), ms per step."""
     import torch
@@ -494,6 +562,9 @@ def main():
              for p in ("f32", "f64")]
             + [measure_rate_gradient(wls.get("codon64") or synth.config_workload("codon64"), p,
                                      max(10, args.steps // 4), 3) for p in ("f32", "bf16")])
+        print("[bench] eigensystem path (phylogeography)", file=sys.stderr, flush=True)
+        geo = synth.geo_workload()
+        line["eigensystem_path"] = [measure_eig(geo, p, max(10, args.steps // 4), 3) for p in ("f64", "f32")]
         print("[bench] autograd modes", file=sys.stderr, flush=True)
         line["autograd"] = [measure_autograd(synth.config_workload("nuc256"), "f32", 20),
                             measure_autograd(synth.config_workload("codon32"), "bf16", 20)]

@@ -15,7 +15,7 @@ from .models import (
 from .trees import Tree, yule_tree, two_taxon_tree, balanced_tree, caterpillar_tree
 from .simulate import simulate_patterns, pattern_weights
 from .workloads import (Workload, make_workload, config_workload, CONFIG_SPECS, serving_dataset,
-                        serving_workload, serving_requests, serving_oracle_sample)
+                        serving_workload, serving_requests, serving_oracle_sample, geo_workload)
 
 __all__ = [
     "NUCLEOTIDES", "CODONS", "GENETIC_CODE", "hky85", "gtr", "jc69", "gy94", "random_aa", "f3x4",
@@ -23,5 +23,5 @@ __all__ = [
     "Tree", "yule_tree", "two_taxon_tree", "balanced_tree", "caterpillar_tree",
     "simulate_patterns", "pattern_weights",
     "Workload", "make_workload", "config_workload", "CONFIG_SPECS", "serving_dataset",
-    "serving_workload", "serving_requests", "serving_oracle_sample",
+    "serving_workload", "serving_requests", "serving_oracle_sample", "geo_workload",
 ]

@@ -188,3 +188,11 @@ def serving_oracle_sample(n_clients: int = 64) -> list:
             out += sorted({rows[0][1], rows[(len(rows) - 1) // 2][1]})
     return out
 
+
+def geo_workload(n_tips: int = 1000, n_states: int = 200, n_categories: int = 4) -> Workload:
+    """Phylogeography-shaped workload for the eigensystem path: one site (each tip's sampled
+    location among n_states), a Yule tree with branches ~ Exp(0.1), random reversible rates
+    between locations, 4 gamma categories.  Seeded by SeedSequence(20260060)."""
+    return make_workload("geo", n_tips, 1, branch_mean=0.1, n_categories=n_categories,
+                         seed=SEED_BASE + 60, name=f"geo{n_states}", n_states=n_states)
+

@@ -3,6 +3,7 @@
     python tests/golden/make_oracle_golden.py nuc8 nuc128 ...
     python tests/golden/make_oracle_golden.py serving     # the serving clients' oracle sample
     python tests/golden/make_oracle_golden.py nuc8_rate nuc128_rate   # rate-matrix gradients
+    python tests/golden/make_oracle_golden.py geo         # the phylogeography workload
 
 For the serving sample, oracle_serving.json holds, per sampled client, lnL and every branch
 gradient at that client's first request.
@@ -68,7 +69,24 @@ def rate_gradient(names):
         print(f"{name} rate gradient in {time.time() - t0:.1f} s", flush=True)
 
 
+def geo():
+    """oracle_geo200.json: lnL and every branch gradient of the phylogeography workload."""
+    t0 = time.time()
+    wl = synth.geo_workload()
+    lnl, _, grad = oracle.lnl_and_grad(wl.tree.children, wl.n_tips, wl.t, wl.Q, wl.pi, wl.rates,
+                                       wl.cat_weights, wl.tips, wl.weights)
+    out = {"workload": wl.name, "n_tips": wl.n_tips, "n_patterns": wl.n_patterns,
+           "n_states": wl.n_states, "lnl": lnl, "grad": grad.tolist(),
+           "oracle_seconds": time.time() - t0}
+    with open(os.path.join(HERE, f"oracle_{wl.name}.json"), "w") as f:
+        json.dump(out, f)
+    print(f"{wl.name}: lnL {lnl:.6f} in {time.time() - t0:.1f} s", flush=True)
+
+
 def main(names):
+    if "geo" in names:
+        geo()
+        names = [n for n in names if n != "geo"]
     if "serving" in names:
         serving()
         names = [n for n in names if n != "serving"]

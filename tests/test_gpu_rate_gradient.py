@@ -123,3 +123,18 @@ def test_matrix_core_path_matches_oracle(precision, kind, n, npat, K, seed):
     nb = 2 * wl.n_tips - 2
     resid = abs(float(np.sum(wl.Q * G)) - float(np.dot(wl.t[:nb], g))) / float(np.sum(np.abs(wl.Q * G)))
     assert resid < (1e-10 if precision == "f64" else tg)
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_codon64_full_size(precision):
+    gold = golden("codon64_rate")
+    if gold is None:
+        pytest.skip("tests/golden/oracle_codon64_rate.json not generated")
+    wl = synth.config_workload("codon64")
+    announce(f"codon64 rate gradient {precision}")
+    inst = make_instance(wl, precision, "every_node")
+    lnl, g, G = inst.evaluate_rate_gradient(wl.t)
+    Go = np.array(gold["rate_grad"])
+    tl, tg = MTOL[precision]
+    print(f"codon64 {precision}: G err {_g_err(G, Go):.2e}")
+    assert rel(lnl, gold["lnl"]) < tl and _g_err(G, Go) < tg
