@@ -22,7 +22,8 @@
  *    are addressed as n_tips..n_tips+n_partials-1 (so a tree's internal node v
  *    can use post buffer v); pre-order partial buffers are 0..n_partials-1.
  *  - Partials are stored on the device as [category][pattern][state] with the
- *    pattern count padded (to a multiple of 128 for n_states <= 4, else of 64)
+ *    pattern count padded (to a multiple of 128 for n_states <= 4, 192 for
+ *    4 < n_states <= 64, none above)
  *    and the state count padded
  *    (hp_query HP_Q_STATE_PAD, HP_Q_PATTERN_PAD); padding patterns carry weight
  *    0 and an unknown state at every tip, so they contribute exactly nothing.

@@ -159,8 +159,9 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     int S_pad;
     if (S <= 4) S_pad = 4;                 // vector-ALU path
     else S_pad = S <= 32 ? 32 : 64;        // matrix-core path: MFMA tiles of 16 states
-    // the 4-state path pads to its largest tile so that the tile can be chosen at creation
-    const int pad = S_pad == 4 ? kWave * kMaxSmallPpl : kWave;
+    // the 4-state path pads to its largest tile so that the tile can be chosen at creation;
+    // the matrix-core path to whole groups of one, two or three 16-pattern tiles
+    const int pad = S_pad == 4 ? kWave * kMaxSmallPpl : 192;
     const int P_pad = (d.n_patterns + pad - 1) / pad * pad;
     const int elem = d.precision == HP_PREC_F64 ? 8 : d.precision == HP_PREC_F32 ? 4 : 2;
     const int celem = d.precision == HP_PREC_F64 ? 8 : 4;  // matrices / Q / freqs: FP64 or FP32
