@@ -18,6 +18,7 @@
 #include <climits>
 
 #include "hp_internal.h"
+#include "lanes.h"
 
 namespace hp {
 namespace {
@@ -94,12 +95,6 @@ __device__ __forceinline__ V4<T> ldexp4(const V4<T>& a, int e) {
     return {ldexp_(a.x, e), ldexp_(a.y, e), ldexp_(a.z, e), ldexp_(a.w, e)};
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
 template <typename T>
 struct WalkDev {
     DescHead h;             // partials [n_out][n_blocks], n_blocks, n_out (read by batched reduce)
@@ -171,8 +166,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 const int p = p0 + j * kWave;
-                double L = 0.0;
-                for (int kk = 0; kk < K; ++kk) L += double(sh_v[s][0][kk][lane + j * kWave]);
+                const double L = cat_sum(sh_v[s][0], K, lane + j * kWave);
                 double l = log(L) + double(E[j]) * 0.69314718055994530942;
                 if (!(L > 0.0) || !isfinite(l)) {
                     atomicOr(a.status, kStatusNumeric);
@@ -272,8 +266,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 __syncthreads();
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
-                    int em = sh_e[s][0][0][lane + j * kWave];
-                    for (int kk = 1; kk < K; ++kk) em = max(em, sh_e[s][0][kk][lane + j * kWave]);
+                    int em = cat_max(sh_e[s][0], K, lane + j * kWave);
                     em = (em == INT_MIN) ? 0 : em;
                     x[j] = ldexp4(x[j], -em);
                     E[j] += em;
@@ -406,12 +399,8 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
                         const int l = lane + j * kWave;
-                        ea[j] = sh_e[s][0][0][l];
-                        eb[j] = sh_e[s][1][0][l];
-                        for (int kk = 1; kk < K; ++kk) {
-                            ea[j] = max(ea[j], sh_e[s][0][kk][l]);
-                            eb[j] = max(eb[j], sh_e[s][1][kk][l]);
-                        }
+                        ea[j] = cat_max(sh_e[s][0], K, l);
+                        eb[j] = cat_max(sh_e[s][1], K, l);
                     }
                 }
                 if (grad) {
@@ -423,11 +412,8 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
 #pragma unroll
                         for (int j = 0; j < PPL; ++j) {
                             const int l = lane + j * kWave;
-                            double den = 0.0, num = 0.0;
-                            for (int kk = 0; kk < K; ++kk) {
-                                den += double(sh_v[s][0][kk][l]);
-                                num += double(sh_v[s][1 + side][kk][l]);
-                            }
+                            const double den = cat_sum(sh_v[s][0], K, l);
+                            const double num = cat_sum(sh_v[s][1 + side], K, l);
                             tot += cp[j] == 0.0 ? 0.0 : cp[j] * (num / den);
                         }
                         tot = wave_sum(tot);
@@ -438,8 +424,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
 #pragma unroll
                         for (int j = 0; j < PPL; ++j) {
                             const int l = lane + j * kWave;
-                            double den = 0.0;
-                            for (int kk = 0; kk < K; ++kk) den += double(sh_v[s][0][kk][l]);
+                            const double den = cat_sum(sh_v[s][0], K, l);
                             const double om = cp[j] == 0.0 ? 0.0 : cp[j] / den;
                             if (g1 >= 0) {
                                 const T f = T(om * a.t_mat[m1]) * wrk;
