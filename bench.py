@@ -51,15 +51,31 @@ def algorithmic_flops(n_tips: int, n_patterns: int, n_states: int, n_cat: int) -
     return 4.0 * (n_tips - 2) * n_patterns * n_cat * 2.0 * n_states ** 2
 
 
+# headers every traversal kernel includes; a change to them changes the kernels too
+KERNEL_HEADERS = ("paper_2606_27607_amd/csrc/hp_internal.h", "paper_2606_27607_amd/csrc/lanes.h")
+
+
+def kernel_sha(kernel_source: str):
+    """sha256 over a kernel source file followed by the shared headers it includes, or None
+    if the source is missing."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in (kernel_source,) + KERNEL_HEADERS:
+        path = os.path.join(ROOT, rel)
+        if not os.path.exists(path):
+            return None
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel_source: str, workload: str, precision: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source (its sha256 must match); None otherwise."""
+    the current kernel source and headers (kernel_sha must match); None otherwise."""
     import glob
-    import hashlib
-    src = os.path.join(ROOT, kernel_source)
-    if not os.path.exists(src):
+    sha = kernel_sha(kernel_source)
+    if sha is None:
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for path in glob.glob(os.path.join(ROOT, "profiles", "*.traffic.json")):
         with open(path) as f:
             rec = json.load(f)
