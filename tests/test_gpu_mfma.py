@@ -120,3 +120,22 @@ def test_codon64_full_size(precision):
           f"grad err {grad_err(g, np.array(gold['grad'])):.3e}")
     assert rel(lnl, gold["lnl"]) < tl
     assert grad_err(g, np.array(gold["grad"])) < tg
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("kind,n,npat,seed", [("gy94", 360, 40, 21), ("aa", 530, 40, 22)])
+def test_large_trees_and_periodic_rescaling(precision, kind, n, npat, seed):
+    """Trees whose tip states exceed the workgroup's LDS staging (N x tile-group bytes over
+    16 KiB, so tip states are read from global memory; FP64's one-tile groups still stage
+    them), each evaluated with rescaling every third level (post-order operations with no
+    exchange between the category waves, exponents forwarded from the previous operation)
+    and at every node."""
+    wl = synth.make_workload(kind, n, npat, seed=seed, unknown_frac=0.05)
+    lnl_o, _, g_o = oracle_eval(wl)
+    tl, tg = TOL[precision]
+    for scaling, period in (("every_k", 3), ("every_node", 1)):
+        inst = make_instance(wl, precision, scaling, period)
+        lnl, g = inst.evaluate(wl.t)
+        assert rel(lnl, lnl_o) < tl, (scaling, lnl, lnl_o)
+        assert grad_err(g, g_o) < tg, scaling
+        inst.close()
