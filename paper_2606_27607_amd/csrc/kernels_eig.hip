@@ -43,12 +43,18 @@ __device__ __forceinline__ size_t col_off(int slot, int kp, int KP, int S_pad) {
 // C[:, col] = A . (scale o B[:, col]) for every column of a level: column j is (node list[j /
 // KP], kp = j % KP); B and C slots are node - b_base and node - c_base.  scale (optional) is
 // E[node][k][:] (the column's e).  One wavefront computes one 16 x 16 output tile on the
-// matrix cores; A (S_pad x S_pad, row-major) is read through L2.
+// matrix cores; A (S_pad x S_pad, row-major) is read through L2.  The contraction runs in
+// chunks of kEigChunk MFMA steps whose operands are loaded one chunk ahead (two register
+// buffers), so each chunk waits on memory once instead of every step waiting on its own
+// loads; the accumulation order is the plain one.
+constexpr int kEigChunk = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(kWave) eig_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
                                                   const int32_t* __restrict__ nodes, int n_cols, int KP, int P,
                                                   int S_pad, int b_base, int c_base, const T* __restrict__ E) {
     using M = EigMfma<T>;
+    constexpr int CH = kEigChunk;
     const int lane = threadIdx.x;
     const int g = lane / 16, jl = lane % 16;
     const int col = blockIdx.x * 16 + jl;
@@ -62,11 +68,32 @@ __global__ void __launch_bounds__(kWave) eig_gemm(const T* __restrict__ A, const
     const T* b = B + col_off(node - b_base, kp, KP, S_pad);
     const T* e = E ? E + ((size_t)node * (KP / P) + kp / P) * S_pad : nullptr;
     const T* a = A + (size_t)(16 * tm + jl) * S_pad;
+    // operands of the steps s = s0, s0 + 4, ... (zero past S_pad: they add nothing)
+    auto load = [&](int s0, T (&av)[CH], T (&bv)[CH], T (&ev)[CH]) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int s = s0 + 4 * u;
+            const bool in = s < S_pad;
+            av[u] = in ? a[s + g] : T(0);
+            bv[u] = in && valid ? b[s + g] : T(0);
+            ev[u] = in && e ? e[s + g] : T(1);
+        }
+    };
     typename M::A4 c = {0, 0, 0, 0};
-    for (int s = 0; s < S_pad; s += 4) {
-        T bv = valid ? b[s + g] : T(0);
-        if (e) bv *= e[s + g];
-        c = M::op(a[s + g], bv, c);
+    auto consume = [&](const T (&av)[CH], const T (&bv)[CH], const T (&ev)[CH]) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u) c = M::op(av[u], e ? bv[u] * ev[u] : bv[u], c);
+    };
+    const int n_ch = (S_pad / 4 + CH - 1) / CH;
+    T a0[CH], b0[CH], e0[CH], a1[CH], b1[CH], e1[CH];
+    load(0, a0, b0, e0);
+    for (int ch = 0; ch < n_ch; ch += 2) {
+        if (ch + 1 < n_ch) load((ch + 1) * 4 * CH, a1, b1, e1);
+        consume(a0, b0, e0);
+        if (ch + 1 < n_ch) {
+            if (ch + 2 < n_ch) load((ch + 2) * 4 * CH, a0, b0, e0);
+            consume(a1, b1, e1);
+        }
     }
     if (valid) {
         T* out = C + col_off(node - c_base, kp, KP, S_pad);
