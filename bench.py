@@ -510,6 +510,8 @@ def main():
                          "spaces, Poisson arrivals), which runs by default")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving benchmark")
     ap.add_argument("--serving-clients", type=int, default=64)
+    ap.add_argument("--eig-only", metavar="PRECISIONS",
+                    help="run only the eigensystem-path leg (geo200), e.g. f64 or f64,f32")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (10 times), the "
                          "reference for scaling HBM byte counters")
@@ -530,6 +532,12 @@ def main():
         sys.exit(2)
 
     import synth
+
+    if args.eig_only:
+        geo = synth.geo_workload()
+        print(json.dumps({"eigensystem_path": [measure_eig(geo, p, max(10, args.steps // 4), 3)
+                                               for p in args.eig_only.split(",")]}), flush=True)
+        return
 
     serving_data = None
     if not args.no_serving or args.serving_only:
