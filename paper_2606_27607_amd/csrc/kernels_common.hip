@@ -22,6 +22,8 @@ namespace {
 template <typename T, typename H>
 __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const int k, const double tt) {
     __shared__ double W[kMaxStates * kMaxStates];  // W[j][y] = exp(lam_j r t) Vinv[j][y]
+    __shared__ double VL[kMaxStates * kMaxStates]; // V
+    __shared__ double ex[kMaxStates];              // exp(lam_j r t)
     __shared__ double rs[kMaxStates];              // rs[j] = exp(lam_j r t) sum_y Vinv[j][y]
     const int K = d.K, S = d.S, S_pad = d.S_pad;
     const int m = d.idx ? d.idx[i] : i;
@@ -31,10 +33,28 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
     const double* V = d.eig;
     const double* Vi = d.eig + S * S;
     const double* lam = d.eig + 2 * S * S;
-    for (int e = threadIdx.x; e < S * S; e += blockDim.x) {
-        const int j = e / S;
-        W[e] = exp(lam[j] * rt) * Vi[e];
+    // V and V^-1 are staged in LDS four elements per thread at a time, so their loads are in
+    // flight together instead of one round trip per element (or per product step)
+    for (int e0 = 0; e0 < S * S; e0 += 4 * (int)blockDim.x) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
+            a[u] = e < S * S ? V[e] : 0.0;
+            b[u] = e < S * S ? Vi[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
+            if (e < S * S) {
+                VL[e] = a[u];
+                W[e] = b[u];
+            }
+        }
     }
+    for (int j = threadIdx.x; j < S; j += blockDim.x) ex[j] = exp(lam[j] * rt);
+    __syncthreads();
+    for (int e = threadIdx.x; e < S * S; e += blockDim.x) W[e] = ex[e / S] * W[e];
     __syncthreads();
     for (int j = threadIdx.x; j < S; j += blockDim.x) {
         double s = 0.0;
@@ -53,7 +73,7 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
         const int x = e / S_pad, y = e % S_pad;
         double v = 0.0;
         if (x < S && y < S)
-            for (int j = 0; j < S; ++j) v += V[x * S + j] * W[j * S + y];
+            for (int j = 0; j < S; ++j) v += VL[x * S + j] * W[j * S + y];
         if (bad) v = NAN;
         Pm[e] = T(v);
         if (y < S) Tt[y * S_pad + x] = T(v);
@@ -73,7 +93,7 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
     for (int x = threadIdx.x; x < S_pad; x += blockDim.x) {
         double v = 0.0;
         if (x < S)
-            for (int j = 0; j < S; ++j) v += V[x * S + j] * rs[j];
+            for (int j = 0; j < S; ++j) v += VL[x * S + j] * rs[j];
         if (bad) v = NAN;
         Tt[S * S_pad + x] = T(v);
     }
