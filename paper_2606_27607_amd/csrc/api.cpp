@@ -138,7 +138,7 @@ int compute_layout_eig(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* el
     l.cat_d = take(2 * kMaxCategories * 8);
     l.t_stage = take(nbr * 8);
     l.idx_stage = take(nbr * 4);
-    l.eig_lists = take((size_t)6 * N * 4);
+    l.eig_lists = take((size_t)8 * N * 4);
     l.eig_children = take((size_t)(2 * N - 1) * 2 * 4);
     l.partials = take((size_t)l.max_out * P * 8);
     l.results = take((size_t)l.max_out * 8);
@@ -938,7 +938,13 @@ static int set_tree_eig(Instance* I, const int32_t* children) {
         lv.n_inner = (int)lists.size() - lv.inner_off;
         plan.pre.push_back(lv);
     }
-    if (lists.size() > (size_t)6 * N) return fail(I, HP_ERR_DEVICE, "level lists exceed their region");
+    // branch gradients need only z, y and e of each branch, none of which a later level
+    // changes: they are formed in one launch after the pre-order levels
+    plan.grad_off = (int)lists.size();
+    for (const auto& lv : plan.pre)
+        lists.insert(lists.end(), lists.begin() + lv.kids_off, lists.begin() + lv.kids_off + lv.n_kids);
+    plan.n_grad = (int)lists.size() - plan.grad_off;
+    if (lists.size() > (size_t)8 * N) return fail(I, HP_ERR_DEVICE, "level lists exceed their region");
     DeviceGuard g(I->d.device);
     rc = upload(I, I->ws + I->L.eig_lists, lists.data(), lists.size() * 4);
     if (rc) return rc;

@@ -140,6 +140,7 @@ struct EigPreLevel {
 };
 struct EigPlan {
     int tips_off = 0;
+    int grad_off = 0, n_grad = 0;   // every non-root node, for the one branch-gradient launch
     std::vector<EigPostLevel> post;
     std::vector<EigPreLevel> pre;
 };

@@ -338,14 +338,16 @@ hipError_t run_eig(const Instance& I, const double* d_t, int want_grad, double* 
             hipLaunchKernelGGL(eig_pre_v<T>, dim3(grid_for((size_t)lv.n * 2 * KP * Sp, 256)), dim3(256), 0, st,
                                lists + lv.off, lv.n, children, Qp, U, W, N, K, P, Sp, freq);
             gemm(Vt, W, Z, lv.kids_off, lv.n_kids, 0, 0, nullptr);          // z_c = V^T v_c
-            hipLaunchKernelGGL(eig_grad<T>, dim3(lv.n_kids * P), dim3(256), 0, st, lists + lv.kids_off, Z, Y, E, lam,
-                               rates, cat_w, pw, rows, K, P, Sp);
             if (lv.n_inner > 0) {
                 gemm(Vit, Z, Qp, lv.inner_off, lv.n_inner, 0, N, E);       // q_c = V^-T (e o z_c)
                 hipLaunchKernelGGL(eig_rescale<T>, dim3(lv.n_inner * P), dim3(256), 0, st, lists + lv.inner_off, Qp,
                                    N, K, P, Sp);
             }
         }
+        // every branch's gradient at once: z, y and e of a branch are final once its level ran
+        if (ep.n_grad > 0)
+            hipLaunchKernelGGL(eig_grad<T>, dim3(ep.n_grad * P), dim3(256), 0, st, lists + ep.grad_off, Z, Y, E, lam,
+                               rates, cat_w, pw, rows, K, P, Sp);
     }
     (void)d_out;   // the host finishes with the fixed-order pattern reduction into d_out
     return hipGetLastError();
