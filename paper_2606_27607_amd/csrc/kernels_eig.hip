@@ -42,20 +42,24 @@ __device__ __forceinline__ size_t col_off(int slot, int kp, int KP, int S_pad) {
 
 // C[:, col] = A . (scale o B[:, col]) for every column of a level: column j is (node list[j /
 // KP], kp = j % KP); B and C slots are node - b_base and node - c_base.  scale (optional) is
-// E[node][k][:] (the column's e).  One wavefront computes one 16 x 16 output tile on the
-// matrix cores; A (S_pad x S_pad, row-major) is read through L2.  The contraction runs in
-// chunks of kEigChunk MFMA steps whose operands are loaded one chunk ahead (two register
-// buffers), so each chunk waits on memory once instead of every step waiting on its own
-// loads; the accumulation order is the plain one.
+// E[node][k][:] (the column's e).  A workgroup computes one 16 x 16 output tile on the
+// matrix cores; A (S_pad x S_pad, row-major) is read through L2.  The contraction is split
+// over the workgroup's kEigSplit waves (consecutive ranges of steps), whose partial tiles are
+// summed in LDS in wave order, so each wave's chain of dependent MFMAs is that much shorter
+// (upper tree levels have few tiles and are bound by that chain).  Within a wave the
+// operands of kEigChunk steps are loaded one chunk ahead, into two register buffers.
 constexpr int kEigChunk = 8;
+constexpr int kEigSplit = 4;
 
 template <typename T>
-__global__ void __launch_bounds__(kWave) eig_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
-                                                  const int32_t* __restrict__ nodes, int n_cols, int KP, int P,
-                                                  int S_pad, int b_base, int c_base, const T* __restrict__ E) {
+__global__ void __launch_bounds__(kWave * kEigSplit)
+eig_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, const int32_t* __restrict__ nodes,
+         int n_cols, int KP, int P, int S_pad, int b_base, int c_base, const T* __restrict__ E) {
     using M = EigMfma<T>;
     constexpr int CH = kEigChunk;
-    const int lane = threadIdx.x;
+    __shared__ typename M::A4 part[kEigSplit - 1][kWave];
+    const int lane = threadIdx.x % kWave;
+    const int w = threadIdx.x / kWave;
     const int g = lane / 16, jl = lane % 16;
     const int col = blockIdx.x * 16 + jl;
     const int tm = blockIdx.y;
@@ -68,12 +72,16 @@ __global__ void __launch_bounds__(kWave) eig_gemm(const T* __restrict__ A, const
     const T* b = B + col_off(node - b_base, kp, KP, S_pad);
     const T* e = E ? E + ((size_t)node * (KP / P) + kp / P) * S_pad : nullptr;
     const T* a = A + (size_t)(16 * tm + jl) * S_pad;
-    // operands of the steps s = s0, s0 + 4, ... (zero past S_pad: they add nothing)
+    // this wave's steps: s in [s_lo, s_hi), multiples of 4
+    const int n_steps = S_pad / 4;
+    const int per = (n_steps + kEigSplit - 1) / kEigSplit;
+    const int s_lo = 4 * min(n_steps, w * per), s_hi = 4 * min(n_steps, (w + 1) * per);
+    // operands of the steps s = s0, s0 + 4, ... (zero past this wave's range: they add nothing)
     auto load = [&](int s0, T (&av)[CH], T (&bv)[CH], T (&ev)[CH]) {
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int s = s0 + 4 * u;
-            const bool in = s < S_pad;
+            const bool in = s < s_hi;
             av[u] = in ? a[s + g] : T(0);
             bv[u] = in && valid ? b[s + g] : T(0);
             ev[u] = in && e ? e[s + g] : T(1);
@@ -84,17 +92,22 @@ __global__ void __launch_bounds__(kWave) eig_gemm(const T* __restrict__ A, const
 #pragma unroll
         for (int u = 0; u < CH; ++u) c = M::op(av[u], e ? bv[u] * ev[u] : bv[u], c);
     };
-    const int n_ch = (S_pad / 4 + CH - 1) / CH;
+    const int n_ch = (s_hi - s_lo + 4 * CH - 1) / (4 * CH);
     T a0[CH], b0[CH], e0[CH], a1[CH], b1[CH], e1[CH];
-    load(0, a0, b0, e0);
+    if (n_ch > 0) load(s_lo, a0, b0, e0);
     for (int ch = 0; ch < n_ch; ch += 2) {
-        if (ch + 1 < n_ch) load((ch + 1) * 4 * CH, a1, b1, e1);
+        if (ch + 1 < n_ch) load(s_lo + (ch + 1) * 4 * CH, a1, b1, e1);
         consume(a0, b0, e0);
         if (ch + 1 < n_ch) {
-            if (ch + 2 < n_ch) load((ch + 2) * 4 * CH, a0, b0, e0);
+            if (ch + 2 < n_ch) load(s_lo + (ch + 2) * 4 * CH, a0, b0, e0);
             consume(a1, b1, e1);
         }
     }
+    if (w > 0) part[w - 1][lane] = c;
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int q = 0; q < kEigSplit - 1; ++q) c += part[q][lane];
     if (valid) {
         T* out = C + col_off(node - c_base, kp, KP, S_pad);
 #pragma unroll
@@ -316,7 +329,7 @@ hipError_t run_eig(const Instance& I, const double* d_t, int want_grad, double* 
         const int n_cols = n_nodes * KP;
         if (n_cols == 0) return;
         dim3 grid((n_cols + 15) / 16, Sp / 16);
-        hipLaunchKernelGGL(eig_gemm<T>, grid, dim3(kWave), 0, st, A, B, C, lists + list_off, n_cols, KP, P, Sp,
+        hipLaunchKernelGGL(eig_gemm<T>, grid, dim3(kWave * kEigSplit), 0, st, A, B, C, lists + list_off, n_cols, KP, P, Sp,
                            b_base, c_base, Es);
     };
     hipLaunchKernelGGL(eig_expo<T>, dim3(grid_for((size_t)nb * K * Sp, 256)), dim3(256), 0, st, E, d_t, lam, rates,
