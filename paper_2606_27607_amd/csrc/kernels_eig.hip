@@ -49,7 +49,7 @@ __device__ __forceinline__ size_t col_off(int slot, int kp, int KP, int S_pad) {
 // (upper tree levels have few tiles and are bound by that chain).  Within a wave the
 // operands of kEigChunk steps are loaded one chunk ahead, into two register buffers.
 constexpr int kEigChunk = 8;
-constexpr int kEigSplit = 4;
+constexpr int kEigSplit = 8;
 
 template <typename T>
 __global__ void __launch_bounds__(kWave * kEigSplit)
