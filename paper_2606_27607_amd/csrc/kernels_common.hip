@@ -19,12 +19,14 @@ namespace {
 // Matrix-core path extras (null when unused): matsT[m][k][y][x] = P[x][y] in T, and 16-bit
 // copies of P and P^T in H (negative rounding residues clamped to 0 before the cast); for
 // BF16 a lo part (value - hi) follows lo_off elements later.
-template <typename T, typename H>
+// SMAX: the padded state count the LDS arrays are sized for (S <= SMAX), so that small
+// state spaces keep many workgroups per CU.
+template <typename T, typename H, int SMAX>
 __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const int k, const double tt) {
-    __shared__ double W[kMaxStates * kMaxStates];  // W[j][y] = exp(lam_j r t) Vinv[j][y]
-    __shared__ double VL[kMaxStates * kMaxStates]; // V
-    __shared__ double ex[kMaxStates];              // exp(lam_j r t)
-    __shared__ double rs[kMaxStates];              // rs[j] = exp(lam_j r t) sum_y Vinv[j][y]
+    __shared__ double W[SMAX * SMAX];              // W[j][y] = exp(lam_j r t) Vinv[j][y]
+    __shared__ double VL[SMAX * SMAX];             // V
+    __shared__ double ex[SMAX];                    // exp(lam_j r t)
+    __shared__ double rs[SMAX];                    // rs[j] = exp(lam_j r t) sum_y Vinv[j][y]
     const int K = d.K, S = d.S, S_pad = d.S_pad;
     const int m = d.idx ? d.idx[i] : i;
     const bool bad = !(tt >= 0.0) || isinf(tt);
@@ -99,18 +101,52 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
     }
 }
 
-template <typename T, typename H>
+template <typename T, typename H, int SMAX>
 __global__ void __launch_bounds__(256) pmat_kernel(const PmatDev d, const double* __restrict__ t) {
-    pmat_body<T, H>(d, blockIdx.x, blockIdx.y, t[blockIdx.x]);
+    pmat_body<T, H, SMAX>(d, blockIdx.x, blockIdx.y, t[blockIdx.x]);
 }
 
-template <typename T, typename H>
+template <typename T, typename H, int SMAX>
 __global__ void __launch_bounds__(256) pmat_batched(const BatchArgs b) {
     const int q = batch_find(b.pmat_off, b.n, blockIdx.x);
     const PmatDev d = load_desc<PmatDev>(b.pmat[q]);
     const int i = blockIdx.x - b.pmat_off[q];
-    pmat_body<T, H>(d, i, blockIdx.y, b.t[q][i]);
+    pmat_body<T, H, SMAX>(d, i, blockIdx.y, b.t[q][i]);
 }
+
+template <typename X>
+struct TypeTag {
+    using type = X;
+};
+
+// The instantiation for the instance's precision and padded state count.
+template <template <typename, typename, int> class Launch, typename... Args>
+void pmat_dispatch(const Instance& I, Args... args) {
+    auto by_states = [&](auto t_tag, auto h_tag) {
+        using T = typename decltype(t_tag)::type;
+        using H = typename decltype(h_tag)::type;
+        if (I.S_pad <= 4) Launch<T, H, 4>::run(I, args...);
+        else if (I.S_pad <= 32) Launch<T, H, 32>::run(I, args...);
+        else Launch<T, H, kMaxStates>::run(I, args...);
+    };
+    switch (I.d.precision) {
+        case HP_PREC_F64: by_states(TypeTag<double>{}, TypeTag<_Float16>{}); break;
+        case HP_PREC_BF16: by_states(TypeTag<float>{}, TypeTag<__bf16>{}); break;
+        default: by_states(TypeTag<float>{}, TypeTag<_Float16>{}); break;
+    }
+}
+template <typename T, typename H, int SMAX>
+struct LaunchPmat {
+    static void run(const Instance& I, dim3 grid, PmatDev d, const double* d_t) {
+        hipLaunchKernelGGL((pmat_kernel<T, H, SMAX>), grid, dim3(256), 0, I.stream, d, d_t);
+    }
+};
+template <typename T, typename H, int SMAX>
+struct LaunchPmatBatched {
+    static void run(const Instance& I, dim3 grid, BatchArgs b) {
+        hipLaunchKernelGGL((pmat_batched<T, H, SMAX>), grid, dim3(256), 0, I.stream, b);
+    }
+};
 
 // out[j] = sum_b partials[j][b] in a fixed order (strided per-thread sums, then a fixed
 // shuffle tree and a fixed order over waves).
@@ -184,21 +220,7 @@ hipError_t launch_pmat(const Instance& I, int eigen_idx, const int32_t* d_idx, c
                        int count) {
     if (count <= 0) return hipSuccess;
     const PmatDev d = build_pmat_desc(I, eigen_idx, d_idx);
-    dim3 grid(count, I.d.n_categories), block(256);
-    switch (I.d.precision) {
-        case HP_PREC_F64:
-            hipLaunchKernelGGL((pmat_kernel<double, _Float16>), grid, block, 0, I.stream, d, d_t);
-            break;
-        case HP_PREC_F32:
-            hipLaunchKernelGGL((pmat_kernel<float, _Float16>), grid, block, 0, I.stream, d, d_t);
-            break;
-        case HP_PREC_BF16:
-            hipLaunchKernelGGL((pmat_kernel<float, __bf16>), grid, block, 0, I.stream, d, d_t);
-            break;
-        default:
-            hipLaunchKernelGGL((pmat_kernel<float, _Float16>), grid, block, 0, I.stream, d, d_t);
-            break;
-    }
+    pmat_dispatch<LaunchPmat>(I, dim3(count, I.d.n_categories), d, d_t);
     return hipGetLastError();
 }
 
@@ -225,12 +247,7 @@ size_t build_tree_desc(const Instance& I, int want_grad, void* host_buf) {
 hipError_t launch_batch(const Instance& I, const BatchArgs& b, int want_grad) {
     if (b.n <= 0) return hipSuccess;
     dim3 gp(b.pmat_off[b.n], I.d.n_categories);
-    switch (I.d.precision) {
-        case HP_PREC_F64: hipLaunchKernelGGL((pmat_batched<double, _Float16>), gp, dim3(256), 0, I.stream, b); break;
-        case HP_PREC_F32: hipLaunchKernelGGL((pmat_batched<float, _Float16>), gp, dim3(256), 0, I.stream, b); break;
-        case HP_PREC_BF16: hipLaunchKernelGGL((pmat_batched<float, __bf16>), gp, dim3(256), 0, I.stream, b); break;
-        default: hipLaunchKernelGGL((pmat_batched<float, _Float16>), gp, dim3(256), 0, I.stream, b); break;
-    }
+    pmat_dispatch<LaunchPmatBatched>(I, gp, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = I.S_pad == 4 ? launch_batch_small(I, b, want_grad) : launch_batch_mfma(I, b, want_grad);
