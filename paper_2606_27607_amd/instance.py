@@ -213,7 +213,8 @@ class Instance:
 
     def evaluate_rate_gradient(self, t):
         """(lnL, d lnL / d t_c for every branch, G): G[i, j] is the first-order approximation
-        of d lnL / d Q_ij for the rate matrix of model slot 0 (n_states <= 4)."""
+        of d lnL / d Q_ij for the rate matrix of model slot 0 (whole-tree instances with
+        n_states <= 64; FP64 with more than 32 padded states needs n_categories <= 4)."""
         self._bind_stream()
         nb = 2 * self.n_tips - 2
         S = self.desc.n_states
