@@ -412,9 +412,22 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
 #pragma unroll
                         for (int j = 0; j < PPL; ++j) {
                             const int l = lane + j * kWave;
-                            const double den = cat_sum(sh_v[s][0], K, l);
-                            const double num = cat_sum(sh_v[s][1 + side], K, l);
-                            tot += cp[j] == 0.0 ? 0.0 : cp[j] * (num / den);
+                            // FP32: the per-pattern ratio in FP32 (its inputs carry FP32 rounding
+                            // already); the weighted pattern sum stays FP64
+                            double r;
+                            if constexpr (sizeof(T) == 4) {
+                                T den = 0, num = 0;
+#pragma unroll
+                                for (int kk = 0; kk < KMAX; ++kk) {
+                                    const T d = sh_v[s][0][kk][l], n = sh_v[s][1 + side][kk][l];
+                                    den += kk < K ? d : T(0);
+                                    num += kk < K ? n : T(0);
+                                }
+                                r = double(num / den);
+                            } else {
+                                r = cat_sum(sh_v[s][1 + side], K, l) / cat_sum(sh_v[s][0], K, l);
+                            }
+                            tot += cp[j] == 0.0 ? 0.0 : cp[j] * r;
                         }
                         tot = wave_sum(tot);
                         if (lane == 0) a.h.partials[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
