@@ -340,8 +340,10 @@ def measure_eig(wl, precision: str, steps: int, warmup: int) -> dict:
             "error_vs_oracle": err}
 
 
-def measure_autograd(wl, precision: str, steps: int) -> dict:
-    """Forward + backward of BranchLengthLnL per mode (store / recompute / fused), ms per step."""
+def measure_autograd(wl, precision: str, steps: int, period: int = 4) -> dict:
+    """Forward + backward of BranchLengthLnL per mode (store / recompute / fused, and the
+    checkpoint variant keeping every period-th level's partials), ms per step and post-order
+    buffers held."""
     import torch
 
     from paper_2606_27607_amd import Instance
@@ -362,8 +364,24 @@ def measure_autograd(wl, precision: str, steps: int) -> dict:
             out = BranchLengthLnL.apply(t, inst, mode)
             (g,) = torch.autograd.grad(out, t)
         torch.cuda.synchronize()
-        res[mode] = {"ms_per_forward_backward": 1000.0 * (time.perf_counter() - t0) / steps}
+        res[mode] = {"ms_per_forward_backward": 1000.0 * (time.perf_counter() - t0) / steps,
+                     "post_buffers": N - 1}
     inst.close()
+    from paper_2606_27607_amd.checkpoint import Checkpointed
+    ck = Checkpointed.create(N, P, S, K, wl.tree.children, period, precision=precision, scaling=scaling[0],
+                             scale_period=scaling[1])
+    ck.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights)
+    for i in range(3 + steps):
+        if i == 3:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        out = BranchLengthLnL.apply(t, ck, "checkpoint")
+        (g,) = torch.autograd.grad(out, t)
+    torch.cuda.synchronize()
+    res[f"checkpoint every {period} levels"] = {
+        "ms_per_forward_backward": 1000.0 * (time.perf_counter() - t0) / steps,
+        "post_buffers": ck.plan.n_post_buffers, "recomputed_segments": ck.plan.n_segments}
+    ck.inst.close()
     return {"workload": f"{wl.name}: {N} taxa, {P} patterns, S={S}", "precision": precision,
             "modes": res}
 

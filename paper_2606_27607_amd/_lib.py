@@ -124,6 +124,20 @@ def check(lib, rc: int, inst=None) -> int:
     return rc
 
 
+def plan_tree(children, scaling: str = "every_k", scale_period: int = 4):
+    """The library's operation lists for a children table: post [N-1, 6] (post-order,
+    children first, with the rescale flags of the policy) and pre [N-1, 9] (parents first)."""
+    import numpy as np
+    lib = load()
+    ch = np.ascontiguousarray(np.asarray(children, dtype=np.int32))
+    n = (ch.shape[0] + 1) // 2
+    post = np.zeros((n - 1, 6), dtype=np.int32)
+    pre = np.zeros((n - 1, 9), dtype=np.int32)
+    check(lib, lib.hp_plan_tree(n, ctypes.c_void_p(ch.ctypes.data), SCALINGS[scaling], int(scale_period),
+                                ctypes.c_void_p(post.ctypes.data), ctypes.c_void_p(pre.ctypes.data)))
+    return post, pre
+
+
 def plan_pre_buffers(children) -> int:
     """Pre-order buffers the whole-tree operation lists need for this children table."""
     import numpy as np

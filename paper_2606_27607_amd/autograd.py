@@ -17,12 +17,16 @@ gradient.  Modes:
 * ``"fused"``     - forward already computes the gradient (one launch for both passes);
                     backward only scales it.  Fastest when every forward is differentiated
                     (gradient-based MCMC and optimisers).
+* ``"checkpoint"`` - ``inst`` is a :class:`~.checkpoint.Checkpointed` instance: forward keeps
+                    the post-order partials of every m-th level only, and backward
+                    recomputes the rest segment by segment (far fewer partial buffers, about
+                    one more post-order pass; the calls block on the host).
 """
 from __future__ import annotations
 
 import torch
 
-MODES = ("store", "recompute", "fused")
+MODES = ("store", "recompute", "fused", "checkpoint")
 
 
 class BranchLengthLnL(torch.autograd.Function):
@@ -33,6 +37,9 @@ class BranchLengthLnL(torch.autograd.Function):
         t = t.detach().contiguous()
         ctx.mode = mode
         ctx.inst = inst
+        if mode == "checkpoint":
+            lnl = inst.lnl(t.cpu().numpy())
+            return torch.tensor(lnl, dtype=torch.float64, device=t.device)
         if mode == "fused":
             out = inst.evaluate_device(t, want_grad=True)
             ctx.save_for_backward(out[1:])
@@ -45,6 +52,9 @@ class BranchLengthLnL(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         inst = ctx.inst
+        if ctx.mode == "checkpoint":
+            g = torch.as_tensor(inst.gradients(), dtype=torch.float64, device=grad_out.device)
+            return grad_out * g, None, None
         if ctx.mode == "fused":
             (g,) = ctx.saved_tensors
         else:

@@ -1,0 +1,187 @@
+"""Branch-length gradients with post-order partials kept only at every m-th level.
+
+Whole-tree evaluation in store mode keeps the post-order partials of all N-1 internal nodes
+from the post-order pass to the pre-order pass.  Here only checkpoint nodes keep theirs:
+internal nodes whose height (edges on the longest path down to a tip) is a multiple of the
+period m, and the root.  The pre-order walk recomputes the partials between checkpoints,
+one segment at a time, just before it needs them: the segment of a non-checkpoint node c is
+c and every internal node below it reached without passing a checkpoint, recomputed from
+the checkpoints and tips under it.  Post-order buffers in use are then the checkpoints
+plus the segments on the current root-to-tip path, instead of N-1, at the cost of about
+one more post-order pass and one launch per segment.
+
+Everything runs through the operation-level calls (hp_update_post, hp_root_lnl,
+hp_pre_gradients) of an instance created with the buffer counts the plan reports; the
+rescale flags are the library's own plan for the instance's scaling policy, so a
+recomputed partial is bitwise the one the forward pass produced.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+
+
+class _Pool:
+    """Buffer ids handed out lowest-first and returned when their contents are consumed."""
+
+    def __init__(self, base: int):
+        self.base, self.free, self.n = base, [], 0
+
+    def take(self) -> int:
+        if self.free:
+            self.free.sort()
+            return self.free.pop(0)
+        self.n += 1
+        return self.base + self.n - 1
+
+    def give(self, b: int) -> None:
+        self.free.append(b)
+
+
+class CheckpointPlan:
+    """Operation lists of the checkpointed evaluation of one tree (host only).
+
+    ``forward_ops``: the post-order list (hp_post_op rows) that leaves every checkpoint's
+    partial in its buffer; ``root_buf``: the root's post buffer; ``steps``: the backward pass
+    as ("post", ops) recomputations and ("pre", ops) pre-order/gradient batches, in order.
+    ``n_post_buffers`` / ``n_pre_buffers`` are the buffer counts the instance needs.
+    """
+
+    def __init__(self, children, period: int, scaling: str = "every_k", scale_period: int = 4):
+        if period < 1:
+            raise ValueError("period must be >= 1")
+        ch = np.asarray(children, dtype=np.int64)
+        N = (ch.shape[0] + 1) // 2
+        self.n_tips, self.period = N, period
+        root = 2 * N - 2
+        post, pre = _lib.plan_tree(ch, scaling, scale_period)
+        self._resc = {int(r[0]): int(r[5]) for r in post}
+        height = np.zeros(2 * N - 1, dtype=np.int64)
+        for r in post:
+            height[r[0]] = 1 + max(height[r[1]], height[r[3]])
+        self.checkpoints = {v for v in range(N, 2 * N - 1) if height[v] % period == 0} | {root}
+        kids = {int(r[0]): (int(r[1]), int(r[3])) for r in post}
+        parent_of = {c: v for v, kv in kids.items() for c in kv}
+
+        # ---- forward: every internal node once; non-checkpoint buffers are recycled as
+        # soon as the parent has combined them
+        pool = _Pool(N)
+        buf = {}
+        fwd = []
+        for r in post:
+            v, a, b = int(r[0]), int(r[1]), int(r[3])
+            buf[v] = pool.take()
+            fwd.append((buf[v], a if a < N else buf[a], a, b if b < N else buf[b], b, self._resc[v]))
+            for c in (a, b):
+                if c >= N and c not in self.checkpoints:
+                    pool.give(buf.pop(c))
+        self.forward_ops = np.array(fwd, dtype=np.int32).reshape(-1, 6)
+        self.root_buf = buf[root]
+        pool.give(buf.pop(root))                       # the backward pass needs only the children
+
+        # ---- backward: the library's pre-order list (parents first); a child whose partial
+        # is not held is recomputed, with its segment, right before the operation using it
+        pre_pool = _Pool(0)
+        pre_buf = {}
+        steps, batch = [], []
+
+        def flush():
+            if batch:
+                steps.append(("pre", np.array(batch, dtype=np.int32).reshape(-1, 9)))
+                batch.clear()
+
+        def recompute(c):
+            seg = []
+            stack = [(c, False)]
+            while stack:                               # post-order over the segment
+                v, done = stack.pop()
+                if done:
+                    seg.append(v)
+                    continue
+                stack.append((v, True))
+                for x in kids[v][::-1]:
+                    if x >= N and x not in buf:
+                        stack.append((x, False))
+            # every recomputed partial stays held until its parent's pre-order operation
+            ops = []
+            for v in seg:
+                a, b = kids[v]
+                buf[v] = pool.take()
+                ops.append((buf[v], a if a < N else buf[a], a, b if b < N else buf[b], b, self._resc[v]))
+            flush()                   # pending pre-order operations still read recycled buffers
+            steps.append(("post", np.array(ops, dtype=np.int32).reshape(-1, 6)))
+
+        for r in pre:
+            a, b = int(r[1]), int(r[5])
+            n = parent_of[a]
+            for c in (a, b):
+                if c >= N and c not in buf:
+                    recompute(c)
+            ca = a if a < N else buf[a]
+            cb = b if b < N else buf[b]
+            qa = -1
+            qb = -1
+            if a >= N:
+                pre_buf[a] = qa = pre_pool.take()
+            if b >= N:
+                pre_buf[b] = qb = pre_pool.take()
+            batch.append((-1 if n == root else pre_buf[n], ca, a, qa, a, cb, b, qb, b))
+            if n != root:
+                pre_pool.give(pre_buf.pop(n))
+            for c in (a, b):                           # a child's partial is read only here
+                if c >= N:
+                    pool.give(buf.pop(c))
+        flush()
+        self.steps = steps
+        self.n_post_buffers = pool.n
+        self.n_pre_buffers = max(1, pre_pool.n)
+
+    @property
+    def n_segments(self) -> int:
+        return sum(1 for kind, _ in self.steps if kind == "post")
+
+
+class Checkpointed:
+    """An instance evaluated through a CheckpointPlan: ``lnl(t)`` (forward, host lnL) then
+    ``gradients()`` (backward, host array of the 2N-2 branch gradients).  ``create`` sizes a
+    new instance for the plan (post-order buffers: the plan's count, not N-1)."""
+
+    @classmethod
+    def create(cls, n_tips, n_patterns, n_states, n_categories, children, period, *,
+               precision="f32", scaling="every_k", scale_period=4, device=0):
+        from .instance import Instance
+        plan = CheckpointPlan(children, period, scaling, scale_period)
+        inst = Instance(n_tips, n_patterns, n_states, n_categories, precision=precision, scaling=scaling,
+                        scale_period=scale_period, n_partials=plan.n_post_buffers,
+                        n_matrices=2 * n_tips - 2, n_pre_partials=plan.n_pre_buffers, device=device)
+        return cls(inst, plan)
+
+    def load(self, tips, weights, V, Vinv, lam, pi, rates, cat_weights):
+        self.inst.load(tips, weights, V, Vinv, lam, pi, rates, cat_weights)
+        return self
+
+    def __init__(self, inst, plan: CheckpointPlan):
+        if inst.n_tips != plan.n_tips:
+            raise ValueError("the instance and the plan differ in taxa")
+        if inst.desc.n_partials < plan.n_post_buffers or \
+                (inst.desc.n_pre_partials or inst.desc.n_partials) < plan.n_pre_buffers:
+            raise ValueError(f"the instance needs n_partials >= {plan.n_post_buffers} and "
+                             f"n_pre_partials >= {plan.n_pre_buffers}")
+        self.inst, self.plan = inst, plan
+
+    def lnl(self, t) -> float:
+        nb = 2 * self.plan.n_tips - 2
+        self.inst.update_matrices(np.arange(nb), np.asarray(t, dtype=np.float64)[:nb])
+        self.inst.update_post(self.plan.forward_ops)
+        return self.inst.root_lnl(self.plan.root_buf)
+
+    def gradients(self) -> np.ndarray:
+        nb = 2 * self.plan.n_tips - 2
+        g = np.zeros(nb)
+        for kind, ops in self.plan.steps:
+            if kind == "post":
+                self.inst.update_post(ops)
+            else:
+                g += self.inst.pre_gradients(ops, nb)
+        return g

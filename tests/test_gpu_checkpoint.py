@@ -1,0 +1,66 @@
+"""GPU parity of checkpointed gradients (post-order partials kept at every m-th level only,
+the rest recomputed in the backward pass) against the FP64 oracle and the store-mode
+whole-tree evaluation, through the operation-level calls."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_helpers import announce, grad_err, make_instance, oracle_eval, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": (1e-12, 1e-9), "f32": (1e-5, 1e-3), "bf16": (1e-4, 5e-2)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def checkpointed(wl, period, precision, scaling, scale_period):
+    from paper_2606_27607_amd.checkpoint import Checkpointed
+    announce(f"checkpointed {wl.name} N={wl.n_tips} P={wl.n_patterns} S={wl.n_states} m={period} {precision}")
+    ck = Checkpointed.create(wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories, wl.tree.children, period,
+                             precision=precision, scaling=scaling, scale_period=scale_period)
+    return ck.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights)
+
+
+@pytest.mark.parametrize("kind,n,npat,precision,period", [
+    ("gtr", 40, 300, "f64", 2), ("gtr", 40, 300, "f64", 3), ("hky", 64, 500, "f32", 4),
+    ("aa", 30, 120, "f32", 2), ("gy94", 24, 80, "bf16", 3)])
+def test_checkpointed_matches_oracle_and_store(kind, n, npat, precision, period):
+    wl = synth.make_workload(kind, n, npat, seed=n + period, unknown_frac=0.05)
+    scaling, sp = ("every_k", 2) if wl.n_states == 4 else ("every_node", 1)
+    ck = checkpointed(wl, period, precision, scaling, sp)
+    assert ck.plan.n_post_buffers < n - 1
+    lnl = ck.lnl(wl.t)
+    g = ck.gradients()
+    lnl_o, _, g_o = oracle_eval(wl)
+    tl, tg = TOL[precision]
+    assert rel(lnl, lnl_o) < tl and grad_err(g, g_o) < tg
+    # store mode runs the whole-tree kernel, which rounds differently (16-bit paths store
+    # u = P post instead of post): both are within the oracle tolerance, so within twice it
+    # of each other
+    store = make_instance(wl, precision, scaling, sp)
+    lnl_s, g_s = store.evaluate(wl.t)
+    assert rel(lnl, lnl_s) < 2 * tl and grad_err(g, g_s) < 2 * tg
+    # a second evaluation at other branch lengths reuses the plan and the buffers
+    t2 = wl.t * 1.3
+    lnl2 = ck.lnl(t2)
+    g2 = ck.gradients()
+    lnl2_o, _, g2_o = oracle_eval(wl, t=t2)
+    assert rel(lnl2, lnl2_o) < tl and grad_err(g2, g2_o) < tg
+
+
+def test_checkpoint_autograd_mode():
+    from paper_2606_27607_amd import autograd
+    wl = synth.make_workload("gtr", 20, 150, seed=5)
+    ck = checkpointed(wl, 2, "f64", "every_k", 2)
+    t = torch.tensor(wl.t[: 2 * wl.n_tips - 2], dtype=torch.float64, device="cuda", requires_grad=True)
+    out = autograd.lnl(t, ck, mode="checkpoint")
+    (3.0 * out).backward()
+    lnl_o, _, g_o = oracle_eval(wl)
+    assert rel(out.item(), lnl_o) < 1e-12
+    assert grad_err(t.grad.cpu().numpy() / 3.0, g_o) < 1e-9
