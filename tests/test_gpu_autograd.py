@@ -60,7 +60,7 @@ def test_modes_agree_bitwise_and_store_detects_reuse():
 
 @pytest.mark.parametrize("name,precision,tol_l,tol_g", [("nuc256", "f32", 1e-5, 1e-3),
                                                         ("codon32", "bf16", 1e-4, 5e-2)])
-@pytest.mark.parametrize("mode", ["store", "recompute"])
+@pytest.mark.parametrize("mode", ["store", "recompute", "checkpoint"])
 def test_differentiation_workloads_full_size(name, precision, tol_l, tol_g, mode):
     import torch
     from paper_2606_27607_amd.autograd import BranchLengthLnL
@@ -70,7 +70,14 @@ def test_differentiation_workloads_full_size(name, precision, tol_l, tol_g, mode
     wl = synth.config_workload(name)
     announce(f"{name} full size {precision} {mode}")
     scaling = ("every_k", 4) if wl.n_states == 4 else ("every_node", 1)
-    inst = make_instance(wl, precision, *scaling)
+    if mode == "checkpoint":
+        # post-order partials kept every 4 levels, the rest recomputed in the backward pass
+        from paper_2606_27607_amd.checkpoint import Checkpointed
+        inst = Checkpointed.create(wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories, wl.tree.children,
+                                   4, precision=precision, scaling=scaling[0], scale_period=scaling[1])
+        inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights)
+    else:
+        inst = make_instance(wl, precision, *scaling)
     nb = 2 * wl.n_tips - 2
     t = torch.tensor(wl.t[:nb], dtype=torch.float64, device="cuda", requires_grad=True)
     out = BranchLengthLnL.apply(t, inst, mode)
