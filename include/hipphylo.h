@@ -30,7 +30,10 @@
  *  - Device memory: the library never allocates device memory.  The caller
  *    sizes a workspace with hp_workspace_bytes, allocates it (any allocator) and
  *    passes it to hp_create; it must outlive the instance.  Host arrays passed to
- *    any call are borrowed for the duration of the call only.
+ *    any call are borrowed for the duration of the call only (per-call arguments such
+ *    as operation lists and branch lengths are copied into pinned staging before the
+ *    call returns; the device copy is stream-ordered, so those calls do not wait for
+ *    the device).
  *  - Streams: all device work is ordered on the instance's HIP stream
  *    (hp_set_stream).  Calls that return results in host memory synchronise that
  *    stream; the *_device variants only enqueue.
@@ -132,6 +135,7 @@ int hp_workspace_bytes(const hp_desc* desc, size_t* out_bytes);
 int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes,
               void* hip_stream, hp_instance** out);
 int hp_destroy(hp_instance* inst);
+/* Work already issued on the previous stream is completed before the switch. */
 int hp_set_stream(hp_instance* inst, void* hip_stream);
 
 /* Copy the message of the last failed call on inst (or of hp_create if inst is NULL)

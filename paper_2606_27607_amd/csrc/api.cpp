@@ -231,6 +231,35 @@ int upload(Instance* I, void* dst, const void* src, size_t bytes) {
     return HP_OK;
 }
 
+// Upload of a per-call argument without waiting for the device: the host array is copied
+// into the next pinned staging slot before return, and the device copy is stream-ordered
+// behind the work already issued (which may still read the destination's previous
+// contents).  A slot is reused only after the copy that last read it has completed.
+int upload_async(Instance* I, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return HP_OK;
+    if (bytes > I->stage_bytes) return upload(I, dst, src, bytes);
+    const int s = I->stage_next;
+    I->stage_next = (s + 1) % Instance::kStageSlots;
+    if (I->stage_pending[s]) {
+        HP_HIP(I, hipEventSynchronize(I->stage_ev[s]));
+        I->stage_pending[s] = false;
+    }
+    std::memcpy(I->host_stage[s], src, bytes);
+    HP_HIP(I, hipMemcpyAsync(dst, I->host_stage[s], bytes, hipMemcpyHostToDevice, I->stream));
+    HP_HIP(I, hipEventRecord(I->stage_ev[s], I->stream));
+    I->stage_pending[s] = true;
+    return HP_OK;
+}
+
+void free_staging(Instance* I) {
+    for (int s = 0; s < Instance::kStageSlots; ++s) {
+        if (I->host_stage[s]) (void)hipHostFree(I->host_stage[s]);
+        if (I->stage_ev[s]) (void)hipEventDestroy(I->stage_ev[s]);
+        I->host_stage[s] = nullptr;
+        I->stage_ev[s] = nullptr;
+    }
+}
+
 template <typename T>
 void store_compute(std::vector<unsigned char>& buf, const std::vector<double>& v) {
     buf.resize(v.size() * sizeof(T));
@@ -418,6 +447,7 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
         std::string m = I->err;
         if (I->host_out) (void)hipHostFree(I->host_out);
         if (I->host_status) (void)hipHostFree(I->host_status);
+        free_staging(I);
         delete I;
         g_create_error = m;
         return code;
@@ -432,6 +462,13 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
     if (hipHostMalloc(reinterpret_cast<void**>(&I->host_out), (size_t)I->L.max_out * 8) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&I->host_status), 64) != hipSuccess)
         return cleanup(fail(I, HP_ERR_DEVICE, "hipHostMalloc of the result staging buffer failed"));
+    I->stage_bytes = std::max({(size_t)max_ops(*desc) * std::max(sizeof(hp_post_op), sizeof(hp_pre_op)),
+                               (size_t)desc->n_matrices * 8, (size_t)(2 * desc->n_tips) * 8});
+    for (int s = 0; s < Instance::kStageSlots; ++s) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&I->host_stage[s]), I->stage_bytes) != hipSuccess ||
+            hipEventCreateWithFlags(&I->stage_ev[s], hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(I, HP_ERR_DEVICE, "allocating the upload staging slots failed"));
+    }
     const int S = desc->n_states, K = desc->n_categories;
     // tips unknown everywhere (padding patterns stay unknown for ever), weights 1 / 0 (padding)
     if (hp::launch_fill_u8(*I, I->at<uint8_t>(I->L.tips), (uint8_t)S, (size_t)desc->n_tips * I->P_pad) ||
@@ -459,6 +496,7 @@ int hp_destroy(hp_instance* inst) {
         for (hipEvent_t e : I->prof.ev) (void)hipEventDestroy(e);
         if (I->host_out) (void)hipHostFree(I->host_out);
         if (I->host_status) (void)hipHostFree(I->host_status);
+        free_staging(I);
     }
     delete I;
     return HP_OK;
@@ -466,7 +504,14 @@ int hp_destroy(hp_instance* inst) {
 
 int hp_set_stream(hp_instance* inst, void* hip_stream) {
     if (!inst) return HP_ERR_ARG;
-    reinterpret_cast<Instance*>(inst)->stream = static_cast<hipStream_t>(hip_stream);
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (static_cast<hipStream_t>(hip_stream) != I->stream) {
+        // work issued on the previous stream (which may still read the staging regions of
+        // the workspace) completes before any work is issued on the new one
+        DeviceGuard g(I->d.device);
+        HP_HIP(I, hipStreamSynchronize(I->stream));
+        I->stream = static_cast<hipStream_t>(hip_stream);
+    }
     return HP_OK;
 }
 
@@ -638,9 +683,9 @@ int hp_update_matrices(hp_instance* inst, int eigen_idx, const int32_t* mat_idx,
         if (!(t[i] >= 0.0) || !std::isfinite(t[i])) return fail(I, HP_ERR_VALUE, "branch length < 0 or not finite");
     }
     DeviceGuard g(I->d.device);
-    int rc = upload(I, I->ws + I->L.idx_stage, mat_idx, (size_t)count * 4);
+    int rc = upload_async(I, I->ws + I->L.idx_stage, mat_idx, (size_t)count * 4);
     if (rc) return rc;
-    rc = upload(I, I->ws + I->L.t_stage, t, (size_t)count * 8);
+    rc = upload_async(I, I->ws + I->L.t_stage, t, (size_t)count * 8);
     if (rc) return rc;
     HP_HIP(I, HP_PMAT(*I, eigen_idx, I->at<int32_t>(I->L.idx_stage), I->at<double>(I->L.t_stage), count));
     return HP_OK;
@@ -664,7 +709,7 @@ int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count) {
         if (o.rescale != 0 && o.rescale != 1) return fail(I, HP_ERR_ARG, "rescale must be 0 or 1");
     }
     DeviceGuard g(I->d.device);
-    int rc = upload(I, I->ws + I->L.ops_stage, ops, (size_t)count * sizeof(hp_post_op));
+    int rc = upload_async(I, I->ws + I->L.ops_stage, ops, (size_t)count * sizeof(hp_post_op));
     if (rc) return rc;
     hp::WalkArgs a;
     a.mode = hp::kPost;
@@ -751,7 +796,7 @@ static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_
     if (rc) return rc;
     DeviceGuard g(I->d.device);
     if (count > 0) {
-        rc = upload(I, I->ws + I->L.ops_stage, ops, (size_t)count * sizeof(hp_pre_op));
+        rc = upload_async(I, I->ws + I->L.ops_stage, ops, (size_t)count * sizeof(hp_pre_op));
         if (rc) return rc;
     }
     hp::WalkArgs a;
@@ -1037,7 +1082,7 @@ int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_l
     for (int c = 0; c < nb; ++c)
         if (!(t[c] >= 0.0) || !std::isfinite(t[c])) return fail(I, HP_ERR_VALUE, "branch length < 0 or not finite");
     DeviceGuard g(I->d.device);
-    rc = upload(I, I->ws + I->L.t_stage, t, (size_t)nb * 8);
+    rc = upload_async(I, I->ws + I->L.t_stage, t, (size_t)nb * 8);
     if (rc) return rc;
     double* d_out = I->at<double>(I->L.results);
     rc = enqueue_evaluate(I, I->at<double>(I->L.t_stage), want_grad, d_out);
@@ -1088,7 +1133,7 @@ int hp_evaluate_rate_gradient(hp_instance* inst, const double* t, double* out_ln
     for (int c = 0; c < nb; ++c)
         if (!(t[c] >= 0.0) || !std::isfinite(t[c])) return fail(I, HP_ERR_VALUE, "branch length < 0 or not finite");
     DeviceGuard g(I->d.device);
-    rc = upload(I, I->ws + I->L.t_stage, t, (size_t)nb * 8);
+    rc = upload_async(I, I->ws + I->L.t_stage, t, (size_t)nb * 8);
     if (rc) return rc;
     double* d_out = I->at<double>(I->L.results);
     rc = enqueue_evaluate(I, I->at<double>(I->L.t_stage), 1, d_out, true);

@@ -160,6 +160,14 @@ struct Instance {
     int tree_n_post = 0, tree_n_pre = 0;
     double* host_out = nullptr;     // pinned host buffer for results
     int32_t* host_status = nullptr; // pinned
+    // pinned host staging of the per-call uploads (operation lists, matrix indices, branch
+    // lengths): a ring of slots, each reused once the copy that last read it has completed
+    static constexpr int kStageSlots = 4;
+    uint8_t* host_stage[kStageSlots] = {};
+    hipEvent_t stage_ev[kStageSlots] = {};
+    bool stage_pending[kStageSlots] = {};
+    int stage_next = 0;
+    size_t stage_bytes = 0;
     Profiler prof;
 
     template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
