@@ -204,6 +204,13 @@ int hp_update_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_i
 int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx,
                      int eigen_idx, double* out_grad, int n_grad);
 
+/* Stream-ordered form of hp_pre_gradients: d_grad is device memory of n_grad FP64 values
+ * and the list's gradients are added to it (slots the list does not name gain +0), so the
+ * batches of one backward pass accumulate into one vector.  Nothing waits for the device;
+ * the operation list is copied before return. */
+int hp_pre_gradients_device(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx,
+                            int eigen_idx, double* d_grad, int n_grad);
+
 /* ---------------------------------------------------------------- whole-tree evaluation */
 
 /* Fix the tree used by hp_evaluate*: children[2N-1][2] (row-major int32) in the standard

@@ -144,8 +144,10 @@ class CheckpointPlan:
 
 class Checkpointed:
     """An instance evaluated through a CheckpointPlan: ``lnl(t)`` (forward, host lnL) then
-    ``gradients()`` (backward, host array of the 2N-2 branch gradients).  ``create`` sizes a
-    new instance for the plan (post-order buffers: the plan's count, not N-1)."""
+    ``gradients()`` (backward, host array of the 2N-2 branch gradients), once per forward
+    pass: the backward pass reuses the segment buffers, so it consumes the forward pass's
+    state.  ``create`` sizes a new instance for the plan (post-order buffers: the plan's
+    count, not N-1)."""
 
     @classmethod
     def create(cls, n_tips, n_patterns, n_states, n_categories, children, period, *,
@@ -177,11 +179,14 @@ class Checkpointed:
         return self.inst.root_lnl(self.plan.root_buf)
 
     def gradients(self) -> np.ndarray:
+        """The 2N-2 branch gradients as a host array.  The pre-order batches add their
+        gradients into one device vector (stream-ordered), so the host waits once."""
+        torch = self.inst.torch
         nb = 2 * self.plan.n_tips - 2
-        g = np.zeros(nb)
+        acc = torch.zeros(nb, dtype=torch.float64, device=self.inst.device)
         for kind, ops in self.plan.steps:
             if kind == "post":
                 self.inst.update_post(ops)
             else:
-                g += self.inst.pre_gradients(ops, nb)
-        return g
+                self.inst.pre_gradients_device(ops, acc)
+        return acc.cpu().numpy()

@@ -777,8 +777,10 @@ static int check_pre_ops(Instance* I, const hp_pre_op* ops, int count, int n_gra
     return HP_OK;
 }
 
+// grad: gradients too, into host out_grad (blocking) or, with on_device, added to device
+// out_grad (stream-ordered)
 static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int eigen_idx,
-                   double* out_grad, int n_grad, bool grad) {
+                   double* out_grad, int n_grad, bool grad, bool on_device = false) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
     if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
@@ -808,6 +810,11 @@ static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_
     a.n_grad = grad ? n_grad : 0;
     HP_HIP(I, HP_WALK(*I, a));
     if (!grad) return HP_OK;
+    if (on_device) {
+        // rows 1 .. n_grad (row 0 is the lnL slot), added to the caller's vector
+        HP_HIP(I, HP_REDUCE(*I, n_grad, out_grad, 1, true));
+        return HP_OK;
+    }
     HP_HIP(I, HP_REDUCE(*I, 1 + n_grad, I->at<double>(I->L.results)));
     HP_HIP(I, hipMemcpyAsync(I->host_out, I->at<double>(I->L.results), (size_t)(1 + n_grad) * 8,
                              hipMemcpyDeviceToHost, I->stream));
@@ -823,6 +830,11 @@ int hp_update_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_i
 int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int eigen_idx,
                      double* out_grad, int n_grad) {
     return run_pre(inst, ops, count, freq_idx, eigen_idx, out_grad, n_grad, true);
+}
+
+int hp_pre_gradients_device(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int eigen_idx,
+                            double* d_grad, int n_grad) {
+    return run_pre(inst, ops, count, freq_idx, eigen_idx, d_grad, n_grad, true, true);
 }
 
 // ------------------------------------------------------------------ whole-tree evaluation

@@ -230,7 +230,7 @@ int small_blocks_per_cu(const Instance& I, int ppl);
 // Pattern tiles per wave of the matrix-core whole-tree kernel and its workgroups per CU.
 void tree_shape_mfma(const Instance& I, int* tiles_per_group, int* blocks_per_cu);
 // out[i] = sum over workgroups of reduction slot first + i, for i < n_out.
-hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first = 0);
+hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first = 0, bool accumulate = false);
 hipError_t launch_fill_i32(const Instance& I, int32_t* p, int32_t v, size_t n);
 hipError_t launch_fill_u8(const Instance& I, uint8_t* p, uint8_t v, size_t n);
 hipError_t launch_fill_f64(const Instance& I, double* p, double v, size_t n);

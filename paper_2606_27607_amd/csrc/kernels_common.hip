@@ -149,9 +149,9 @@ struct LaunchPmatBatched {
 };
 
 // out[j] = sum_b partials[j][b] in a fixed order (strided per-thread sums, then a fixed
-// shuffle tree and a fixed order over waves).
+// shuffle tree and a fixed order over waves); with accumulate, out[j] += that sum.
 __global__ void __launch_bounds__(256)
-reduce_rows(const double* __restrict__ partials, int n_blocks, int first, double* __restrict__ out) {
+reduce_rows(const double* __restrict__ partials, int n_blocks, int first, double* __restrict__ out, int accumulate) {
     __shared__ double ws[4];
     const int j = first + blockIdx.x;
     double s = 0.0;
@@ -160,7 +160,10 @@ reduce_rows(const double* __restrict__ partials, int n_blocks, int first, double
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
     if ((threadIdx.x % kWave) == 0) ws[threadIdx.x / kWave] = s;
     __syncthreads();
-    if (threadIdx.x == 0) out[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+    if (threadIdx.x == 0) {
+        const double v = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+        out[blockIdx.x] = accumulate ? out[blockIdx.x] + v : v;
+    }
 }
 
 // Batched second-stage reduction: block -> (instance, slot); the instance's reduction rows
@@ -261,10 +264,10 @@ hipError_t launch_walk(const Instance& I, const WalkArgs& w) {
     return launch_walk_mfma(I, w);
 }
 
-hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first) {
+hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first, bool accumulate) {
     if (n_out <= 0) return hipSuccess;
     hipLaunchKernelGGL(reduce_rows, dim3(n_out), dim3(256), 0, I.stream, I.at<double>(I.L.partials),
-                       I.n_blocks, first, d_out);
+                       I.n_blocks, first, d_out, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -180,6 +180,19 @@ class Instance:
                    _ptr(g), int(n_grad))
         return g[:n_grad]
 
+    def pre_gradients_device(self, ops, acc, freq_idx: int = 0, eigen_idx: int = 0):
+        """Stream-ordered form of :meth:`pre_gradients`: the list's gradients are added to
+        ``acc`` (a contiguous CUDA float64 tensor of n_grad values; slots the list does not
+        name gain +0).  Returns ``acc``."""
+        self._bind_stream()
+        torch = self.torch
+        if not (acc.is_cuda and acc.dtype == torch.float64 and acc.is_contiguous() and acc.numel() >= 1):
+            raise ValueError("acc must be a contiguous CUDA float64 tensor")
+        o = _i32(ops).reshape(-1, 9)
+        self._call("hp_pre_gradients_device", _ptr(o), int(o.shape[0]), int(freq_idx), int(eigen_idx),
+                   ctypes.c_void_p(acc.data_ptr()), int(acc.numel()))
+        return acc
+
     # ------------------------------------------------------------------ whole tree
     def set_tree(self, children):
         c = _i32(children).reshape(-1, 2)

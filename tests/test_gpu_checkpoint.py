@@ -54,6 +54,28 @@ def test_checkpointed_matches_oracle_and_store(kind, n, npat, precision, period)
     assert rel(lnl2, lnl2_o) < tl and grad_err(g2, g2_o) < tg
 
 
+def test_device_accumulation_equals_host_batches():
+    """The stream-ordered pre-order gradient batches summed on the device give bitwise the
+    host-returned batches summed on the host (each slot gains exactly one nonzero term)."""
+    wl = synth.make_workload("gtr", 48, 400, seed=4)
+    ck = checkpointed(wl, 3, "f32", "every_k", 2)
+    ck.lnl(wl.t)
+    g_dev = ck.gradients()
+    nb = 2 * wl.n_tips - 2
+    ck.lnl(wl.t)                 # the backward pass consumes the forward pass's buffers
+    g_host = np.zeros(nb)
+    for kind, ops in ck.plan.steps:
+        if kind == "post":
+            ck.inst.update_post(ops)
+        else:
+            g_host += ck.inst.pre_gradients(ops, nb)
+    assert np.array_equal(g_dev, g_host)
+    # a list that names no slot adds zero everywhere
+    acc = torch.arange(nb, dtype=torch.float64, device="cuda")
+    ck.inst.pre_gradients_device(np.zeros((0, 9), dtype=np.int32), acc)
+    assert torch.equal(acc.cpu(), torch.arange(nb, dtype=torch.float64))
+
+
 def test_checkpoint_autograd_mode():
     from paper_2606_27607_amd import autograd
     wl = synth.make_workload("gtr", 20, 150, seed=5)
