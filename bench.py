@@ -147,18 +147,16 @@ def measure(wl, precision: str, steps: int, warmup: int, latency_samples: int) -
     import numpy as np
     import torch
 
-    from paper_2606_27607_amd import Instance
+    from paper_2606_27607_amd import Instance, default_scaling
 
     N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
     nb = 2 * N - 2
     small = S <= 4
+    policy, period = default_scaling(S, precision)
     if small:
-        period = max(1, wl.meta.get("scale_every", 4))
-        inst = Instance(N, P, S, K, precision=precision, scaling="every_k", scale_period=period)
-        scaling = f"rescaling every {period} levels"
-    else:
-        inst = Instance(N, P, S, K, precision=precision, scaling="every_node")
-        scaling = "rescaling every node"
+        period = max(1, wl.meta.get("scale_every", period))
+    inst = Instance(N, P, S, K, precision=precision, scaling=policy, scale_period=period)
+    scaling = f"rescaling every {period} levels" if policy == "every_k" else "rescaling every node"
     inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
               children=wl.tree.children)
     dev = inst.device
@@ -249,15 +247,14 @@ def measure_rate_gradient(wl, precision: str, steps: int, warmup: int) -> dict:
     import numpy as np
     import torch
 
-    from paper_2606_27607_amd import Instance
+    from paper_2606_27607_amd import Instance, default_scaling
 
     N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
     nb = 2 * N - 2
+    policy, period = default_scaling(S, precision)
     if S <= 4:
-        inst = Instance(N, P, S, K, precision=precision, scaling="every_k",
-                        scale_period=max(1, wl.meta.get("scale_every", 4)))
-    else:
-        inst = Instance(N, P, S, K, precision=precision, scaling="every_node")
+        period = max(1, wl.meta.get("scale_every", period))
+    inst = Instance(N, P, S, K, precision=precision, scaling=policy, scale_period=period)
     inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
               children=wl.tree.children)
     rng = np.random.default_rng(2)
@@ -324,7 +321,7 @@ def measure_eig(wl, precision: str, steps: int, warmup: int) -> dict:
     import numpy as np
     import torch
 
-    from paper_2606_27607_amd import Instance
+    from paper_2606_27607_amd import Instance, default_scaling
 
     N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
     nb = 2 * N - 2
@@ -382,11 +379,11 @@ def measure_autograd(wl, precision: str, steps: int, period: int = 4) -> dict:
     buffers held."""
     import torch
 
-    from paper_2606_27607_amd import Instance
+    from paper_2606_27607_amd import Instance, default_scaling
     from paper_2606_27607_amd.autograd import BranchLengthLnL
 
     N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
-    scaling = ("every_k", 4) if S <= 4 else ("every_node", 1)
+    scaling = default_scaling(S, precision)
     inst = Instance(N, P, S, K, precision=precision, scaling=scaling[0], scale_period=scaling[1])
     inst.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
               children=wl.tree.children)

@@ -4,7 +4,7 @@ The compute path is the HIP library ``libhipphylo.so`` (C ABI in include/hipphyl
 this package is its Python binding.  Importing :class:`Instance` loads the library and
 raises if it has not been built - there is no CPU fallback.
 """
-from ._lib import HPError, load as load_library  # noqa: F401
+from ._lib import HPError, default_scaling, load as load_library  # noqa: F401
 
 
 def __getattr__(name):
@@ -14,4 +14,4 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-__all__ = ["Instance", "HPError", "load_library"]
+__all__ = ["Instance", "HPError", "default_scaling", "load_library"]

@@ -30,6 +30,17 @@ ERROR_NAMES = {
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 SCALINGS = {"none": 0, "every_node": 1, "every_k": 2}
 
+
+def default_scaling(n_states: int, precision: str):
+    """The rescaling policy used for a state space and precision, as (scaling, period):
+    every node for FP16 partials (5-bit exponent) and for more than 64 states (the
+    eigensystem path, whose single-pattern partials shrink by about 1/S per tip), otherwise
+    every 4 levels: FP32, BF16 and FP64 keep 8 or more exponent bits, and between rescaled
+    nodes a partial combines at most 2^4 tips."""
+    if precision == "f16" or n_states > 64:
+        return ("every_node", 1)
+    return ("every_k", 4)
+
 HP_Q_STATE_PAD = 1
 HP_Q_PATTERN_PAD = 2
 HP_Q_ELEMENT_BYTES = 3

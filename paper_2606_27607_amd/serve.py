@@ -78,8 +78,8 @@ class Dataset:
                        self.Vinv, self.lam, self.pi, self.rates, self.cat_weights, self.children)
 
 
-def scaling_for(n_states):
-    return ("every_k", 4) if n_states <= 4 else ("every_node", 1)
+def scaling_for(n_states, precision):
+    return _lib.default_scaling(n_states, precision)
 
 
 class DeviceMemory:
@@ -194,7 +194,7 @@ class HipExecutor:
         return data._n_pre
 
     def footprint(self, data: Dataset, precision: str) -> int:
-        sc = scaling_for(data.n_states)
+        sc = scaling_for(data.n_states, precision)
         d = _lib.hp_desc(n_tips=data.n_tips, n_patterns=data.n_patterns, n_states=data.n_states,
                          n_categories=len(data.rates), n_partials=data.n_tips - 1,
                          n_matrices=2 * data.n_tips - 2, n_eigen=1,
@@ -209,7 +209,7 @@ class HipExecutor:
         torch = self.torch
         from .instance import Instance
         d = s.data
-        sc = scaling_for(d.n_states)
+        sc = scaling_for(d.n_states, s.precision)
         if self.arena is None:
             raise RuntimeError("HipExecutor.reserve was not called")
         ptr = self.arena.alloc(s.footprint)

@@ -24,13 +24,15 @@ def _mixed_workloads():
     return [synth.make_workload(k, n, p, seed=s, unknown_frac=0.03) for k, n, p, s in specs]
 
 
+@pytest.mark.parametrize("policy", ["every_k", "every_node"])
 @pytest.mark.parametrize("cls", ["nuc", "codon", "aa"])
-def test_batched_launch_equals_alone(cls):
+def test_batched_launch_equals_alone(cls, policy):
     import torch
     from paper_2606_27607_amd import _lib
     S = {"nuc": 4, "codon": 61, "aa": 20}[cls]
     wls = [w for w in _mixed_workloads() if w.n_states == S]
-    prec, scaling = ("f32", ("every_k", 4)) if cls == "nuc" else ("bf16", ("every_node", 1))
+    prec = "f32" if cls == "nuc" else "bf16"
+    scaling = ("every_k", 4) if policy == "every_k" else ("every_node", 1)
     insts = [make_instance(w, prec, *scaling) for w in wls]
     ts = [torch.tensor(w.t[: 2 * w.n_tips - 2] * 1.1, dtype=torch.float64, device="cuda") for w in wls]
     alone = [inst.evaluate_device(t).clone() for inst, t in zip(insts, ts)]
@@ -92,8 +94,8 @@ def test_server_mix_equals_alone(budget_frac):
     # alone: each request on a fresh instance of its own, one at a time
     alone = {}
     for c, w in enumerate(wls):
-        sc = ("every_k", 4) if w.n_states == 4 else ("every_node", 1)
-        alone[c] = make_instance(w, prec[w.n_states], *sc)
+        from paper_2606_27607_amd import default_scaling
+        alone[c] = make_instance(w, prec[w.n_states], *default_scaling(w.n_states, prec[w.n_states]))
     for (c, t), (lnl, g) in zip(reqs, results):
         lnl_a, g_a = alone[c].evaluate(t)
         assert lnl == lnl_a and np.array_equal(g, g_a), c
