@@ -216,3 +216,21 @@ def test_large_state_spaces_fp64_fp32_only(lib):
         vec = 98 * 4 * 3 * 208 * (8 if prec == 0 else 4)      # one per-branch vector array
         assert 4 * vec < n < 12 * vec
     assert ws_bytes(lib, desc(n_states=200, precision=2))[0] == _lib.HP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("S,precision,expect", [
+    (4, "f32", ("every_k", 4)), (4, "f64", ("every_k", 4)), (61, "bf16", ("every_k", 4)),
+    (20, "f32", ("every_k", 4)), (61, "f16", ("every_node", 1)), (20, "f16", ("every_node", 1)),
+    (200, "f64", ("every_node", 1)), (65, "f32", ("every_node", 1))])
+def test_default_scaling_policy(S, precision, expect):
+    """Every 4 levels where partials keep an 8-bit or wider exponent; every node for FP16
+    partials and for the eigensystem path (more than 64 states)."""
+    assert _lib.default_scaling(S, precision) == expect
+    # and the policy is one the library accepts for that state space and precision
+    d = _lib.hp_desc(n_tips=16, n_patterns=100, n_states=S, n_categories=4, n_partials=15,
+                     n_matrices=30, n_eigen=1, precision=_lib.PRECISIONS[precision],
+                     scaling=_lib.SCALINGS[expect[0]], scale_period=expect[1], device=0)
+    if S > 64 and precision not in ("f32", "f64"):
+        return
+    n = ctypes.c_size_t()
+    assert _lib.load().hp_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == 0 and n.value > 0
