@@ -169,7 +169,8 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     Layout l{};
     const bool mfma = S_pad > 4;
     l.tile = mfma ? kMfmaTile : kWave;  // 4-state path: the smallest tile, sizing the partials
-    l.n_blocks = (d.n_patterns + l.tile - 1) / l.tile;
+    // matrix-core path: one reduction column per padded tile (operation-level launches)
+    l.n_blocks = mfma ? P_pad / l.tile : (d.n_patterns + l.tile - 1) / l.tile;
     if (mfma && l.n_blocks > kMaxMfmaBlocks) l.n_blocks = kMaxMfmaBlocks;
     const int n_blocks = l.n_blocks;
     l.post_stride = (size_t)K * P_pad * S_pad;
@@ -384,15 +385,28 @@ void choose_small_tile(Instance* I) {
     I->L.n_blocks = I->n_blocks = (P + I->L.tile - 1) / I->L.tile;
 }
 
+// Workgroups of an operation-level traversal launch (the columns its reduction rows use).
+int op_blocks(const Instance* I) { return I->S_pad > 4 ? I->n_blocks_op : I->n_blocks; }
+
 // Workgroups of a matrix-core launch.  Each walks groups of pattern tiles in a grid-stride
 // loop, so launching no more workgroups than the device holds at once keeps the whole grid
 // resident and balances it to within one group per workgroup; never more than there are
 // groups (an idle workgroup still zeroes its reduction column).
 void choose_mfma_blocks(Instance* I) {
-    int ct = 1, per_cu = 0, n_cu = 0;
-    hp::tree_shape_mfma(*I, &ct, &per_cu);
+    int ct = 1, per_cu = 0, op_per_cu = 0, n_cu = 0;
+    hp::tree_shape_mfma(*I, &ct, &per_cu, &op_per_cu);
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, I->d.device) != hipSuccess)
         n_cu = 0;
+    // operation-level launches: a workgroup per tile, but no more than the pre-order kernel
+    // (the heaviest) holds at once, so that its tiles never run in a second partial round;
+    // as many as the reduction rows hold (HIPPHYLO_OP_BLOCKS overrides the count, tuning)
+    int op = I->P_pad / hp::kMfmaTile;
+    if (op_per_cu > 0 && n_cu > 0) op = std::min(op, op_per_cu * n_cu);
+    if (const char* env = std::getenv("HIPPHYLO_OP_BLOCKS")) {
+        const int v = std::atoi(env);
+        if (v >= 1) op = v;
+    }
+    I->n_blocks_op = std::max(1, std::min(op, I->L.n_blocks));
     const long groups = (long)(I->P_pad / hp::kMfmaTile) / ct;
     long nb = groups;
     if (per_cu > 0 && n_cu > 0) nb = std::min(nb, (long)per_cu * n_cu);
@@ -735,7 +749,7 @@ int hp_root_lnl(hp_instance* inst, int root_buf, int freq_idx, double* out_lnl, 
     a.freq_idx = freq_idx;
     a.site = out_site ? I->at<double>(I->L.site) : nullptr;
     HP_HIP(I, HP_WALK(*I, a));
-    HP_HIP(I, HP_REDUCE(*I, 1, I->at<double>(I->L.results)));
+    HP_HIP(I, HP_REDUCE(*I, 1, I->at<double>(I->L.results), 0, false, op_blocks(I)));
     HP_HIP(I, hipMemcpyAsync(I->host_out, I->at<double>(I->L.results), 8, hipMemcpyDeviceToHost, I->stream));
     if (out_site)
         HP_HIP(I, hipMemcpyAsync(out_site, I->at<double>(I->L.site), (size_t)I->d.n_patterns * 8,
@@ -812,10 +826,10 @@ static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_
     if (!grad) return HP_OK;
     if (on_device) {
         // rows 1 .. n_grad (row 0 is the lnL slot), added to the caller's vector
-        HP_HIP(I, HP_REDUCE(*I, n_grad, out_grad, 1, true));
+        HP_HIP(I, HP_REDUCE(*I, n_grad, out_grad, 1, true, op_blocks(I)));
         return HP_OK;
     }
-    HP_HIP(I, HP_REDUCE(*I, 1 + n_grad, I->at<double>(I->L.results)));
+    HP_HIP(I, HP_REDUCE(*I, 1 + n_grad, I->at<double>(I->L.results), 0, false, op_blocks(I)));
     HP_HIP(I, hipMemcpyAsync(I->host_out, I->at<double>(I->L.results), (size_t)(1 + n_grad) * 8,
                              hipMemcpyDeviceToHost, I->stream));
     HP_HIP(I, hipStreamSynchronize(I->stream));

@@ -150,6 +150,9 @@ struct Instance {
     bool eig = false;               // 64 < S: transition matrices applied through the eigensystem
     EigPlan eig_plan;
     int S_pad = 0, P_pad = 0, elem = 0, n_blocks = 0;
+    // workgroups of an operation-level launch on the matrix-core path: one per 16-pattern
+    // tile (the whole-tree kernel's n_blocks counts groups of several tiles)
+    int n_blocks_op = 0;
     hipStream_t stream = nullptr;
     uint8_t* ws = nullptr;
     size_t ws_bytes = 0;
@@ -228,9 +231,13 @@ hipError_t launch_eig_evaluate(const Instance& I, const double* d_t, int want_gr
 // Workgroups of the 4-state whole-tree kernel one CU holds with `ppl` patterns per lane.
 int small_blocks_per_cu(const Instance& I, int ppl);
 // Pattern tiles per wave of the matrix-core whole-tree kernel and its workgroups per CU.
-void tree_shape_mfma(const Instance& I, int* tiles_per_group, int* blocks_per_cu);
+// Tiles per group and resident workgroups per CU of the whole-tree kernel, and resident
+// workgroups per CU of the operation-level pre-order kernel (the heaviest one).
+void tree_shape_mfma(const Instance& I, int* tiles_per_group, int* blocks_per_cu, int* op_blocks_per_cu);
 // out[i] = sum over workgroups of reduction slot first + i, for i < n_out.
-hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first = 0, bool accumulate = false);
+// n_blocks: the traversal launch's workgroups (0: I.n_blocks)
+hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first = 0, bool accumulate = false,
+                         int n_blocks = 0);
 hipError_t launch_fill_i32(const Instance& I, int32_t* p, int32_t v, size_t n);
 hipError_t launch_fill_u8(const Instance& I, uint8_t* p, uint8_t v, size_t n);
 hipError_t launch_fill_f64(const Instance& I, double* p, double v, size_t n);

@@ -264,10 +264,10 @@ hipError_t launch_walk(const Instance& I, const WalkArgs& w) {
     return launch_walk_mfma(I, w);
 }
 
-hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first, bool accumulate) {
+hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first, bool accumulate, int n_blocks) {
     if (n_out <= 0) return hipSuccess;
     hipLaunchKernelGGL(reduce_rows, dim3(n_out), dim3(256), 0, I.stream, I.at<double>(I.L.partials),
-                       I.n_blocks, first, d_out, accumulate ? 1 : 0);
+                       n_blocks > 0 ? n_blocks : I.n_blocks, first, d_out, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -17,17 +17,17 @@ hipError_t launch_batch_mfma_f32(const Instance& I, const BatchArgs& b, int want
 hipError_t launch_batch_mfma_bf16(const Instance& I, const BatchArgs& b, int want_grad);
 hipError_t launch_batch_mfma_f16(const Instance& I, const BatchArgs& b, int want_grad);
 
-void tree_shape_mfma_f64(const Instance& I, int* tiles_per_group, int* blocks_per_cu);
-void tree_shape_mfma_f32(const Instance& I, int* tiles_per_group, int* blocks_per_cu);
-void tree_shape_mfma_bf16(const Instance& I, int* tiles_per_group, int* blocks_per_cu);
-void tree_shape_mfma_f16(const Instance& I, int* tiles_per_group, int* blocks_per_cu);
+void tree_shape_mfma_f64(const Instance& I, int* tiles_per_group, int* blocks_per_cu, int* op_blocks_per_cu);
+void tree_shape_mfma_f32(const Instance& I, int* tiles_per_group, int* blocks_per_cu, int* op_blocks_per_cu);
+void tree_shape_mfma_bf16(const Instance& I, int* tiles_per_group, int* blocks_per_cu, int* op_blocks_per_cu);
+void tree_shape_mfma_f16(const Instance& I, int* tiles_per_group, int* blocks_per_cu, int* op_blocks_per_cu);
 
-void tree_shape_mfma(const Instance& I, int* tiles_per_group, int* blocks_per_cu) {
+void tree_shape_mfma(const Instance& I, int* tiles_per_group, int* blocks_per_cu, int* op_blocks_per_cu) {
     switch (I.d.precision) {
-        case HP_PREC_F64: tree_shape_mfma_f64(I, tiles_per_group, blocks_per_cu); break;
-        case HP_PREC_F32: tree_shape_mfma_f32(I, tiles_per_group, blocks_per_cu); break;
-        case HP_PREC_BF16: tree_shape_mfma_bf16(I, tiles_per_group, blocks_per_cu); break;
-        default: tree_shape_mfma_f16(I, tiles_per_group, blocks_per_cu); break;
+        case HP_PREC_F64: tree_shape_mfma_f64(I, tiles_per_group, blocks_per_cu, op_blocks_per_cu); break;
+        case HP_PREC_F32: tree_shape_mfma_f32(I, tiles_per_group, blocks_per_cu, op_blocks_per_cu); break;
+        case HP_PREC_BF16: tree_shape_mfma_bf16(I, tiles_per_group, blocks_per_cu, op_blocks_per_cu); break;
+        default: tree_shape_mfma_f16(I, tiles_per_group, blocks_per_cu, op_blocks_per_cu); break;
     }
 }
 

@@ -9,7 +9,7 @@ size_t build_tree_desc_mfma_f32(const Instance& I, const WalkArgs& w, void* buf)
 hipError_t launch_batch_mfma_f32(const Instance& I, const BatchArgs& b, int want_grad) {
     return batch_precision<HP_PREC_F32>(I, b, want_grad);
 }
-void tree_shape_mfma_f32(const Instance& I, int* tiles_per_group, int* blocks_per_cu) {
-    shape_precision<HP_PREC_F32>(I, tiles_per_group, blocks_per_cu);
+void tree_shape_mfma_f32(const Instance& I, int* tiles_per_group, int* blocks_per_cu, int* op_blocks_per_cu) {
+    shape_precision<HP_PREC_F32>(I, tiles_per_group, blocks_per_cu, op_blocks_per_cu);
 }
 }  // namespace hp
