@@ -91,6 +91,27 @@ def test_op_level_api_mfma(precision):
     assert grad_err(g, g_o) < tg
 
 
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_op_level_more_tiles_than_resident_workgroups(precision):
+    """Operation-level launches hold at most one workgroup per tile that the device keeps
+    resident (768 for 64 padded states): 14,000 patterns (876 tiles) make workgroups walk a
+    second tile in their grid-stride loop, and the reduction columns follow the launch."""
+    from paper_2606_27607_amd import _lib
+    wl = synth.make_workload("gy94", 5, 14000, seed=31, unknown_frac=0.05)
+    inst = make_instance(wl, precision, "every_node", tree=False)
+    announce(f"op-level gy94 N=5 P=14000 {precision}")
+    N = wl.n_tips
+    nb = 2 * N - 2
+    inst.update_matrices(np.arange(nb), wl.t[:nb])
+    inst.update_post(post_ops(wl.tree.children, N, rescale=1))
+    lnl = inst.root_lnl(2 * N - 2)
+    g = inst.pre_gradients(pre_ops(wl.tree.children, N), nb)
+    lnl_o, _, g_o = oracle_eval(wl)
+    tl, tg = TOL[precision]
+    assert rel(lnl, lnl_o) < tl and grad_err(g, g_o) < tg
+    assert inst.query(_lib.HP_Q_PATTERN_PAD) // 16 == 876
+
+
 @pytest.mark.parametrize("kind,precision", [("aa", "f32"), ("gy94", "f16"), ("gy94", "bf16")])
 def test_many_tiles_per_workgroup_and_determinism(kind, precision):
     """More tile groups than the device holds workgroups at once: the launch is sized to the
