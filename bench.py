@@ -579,7 +579,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the pattern "
-              "partition across GPUs is a design note, not part of this build)", file=sys.stderr)
+              "partition across GPUs is described in the design notes and not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import synth
