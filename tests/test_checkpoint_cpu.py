@@ -58,7 +58,7 @@ def simulate(plan, children):
 
 
 @pytest.mark.parametrize("n,seed", [(2, 0), (3, 1), (9, 2), (64, 3), (256, 4)])
-@pytest.mark.parametrize("period", [1, 2, 3, 4])
+@pytest.mark.parametrize("period", [1, 2, 3, 4, 1000])
 def test_plan_feeds_every_operation_its_partials(n, seed, period):
     tree = synth.trees.yule_tree(n, np.random.default_rng(seed)) if n > 2 else None
     children = tree.children if tree is not None else np.array([[-1, -1], [-1, -1], [0, 1]])
@@ -82,3 +82,15 @@ def test_caterpillar_and_buffer_savings():
     simulate(ck, yule)
     assert store.n_post_buffers >= 255 and ck.n_post_buffers < store.n_post_buffers // 2
     assert ck.n_segments > 0 and store.n_segments == 0
+
+
+def test_period_beyond_height_keeps_only_the_root():
+    """With m above the tree height only the root is a checkpoint: the backward pass then
+    recomputes every other internal node, in segments below the root's children."""
+    yule = synth.trees.yule_tree(40, np.random.default_rng(3)).children
+    plan = CheckpointPlan(yule, 10_000)
+    simulate(plan, yule)
+    assert list(plan.checkpoints) == [2 * 40 - 2]
+    recomputed = sum(len(ops) for kind, ops in plan.steps if kind == "post")
+    assert recomputed == 40 - 2          # every internal node but the root, exactly once
+
