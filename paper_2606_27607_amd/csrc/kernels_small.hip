@@ -412,8 +412,9 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
 #pragma unroll
                         for (int j = 0; j < PPL; ++j) {
                             const int l = lane + j * kWave;
-                            // FP32: the per-pattern ratio in FP32 (its inputs carry FP32 rounding
-                            // already); the weighted pattern sum stays FP64
+                            // FP32: the per-pattern ratio in FP32 with the hardware reciprocal
+                            // (1 ulp; its inputs carry FP32 rounding already); the weighted
+                            // pattern sum stays FP64
                             double r;
                             if constexpr (sizeof(T) == 4) {
                                 T den = 0, num = 0;
@@ -423,7 +424,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                                     den += kk < K ? d : T(0);
                                     num += kk < K ? n : T(0);
                                 }
-                                r = double(num / den);
+                                r = double(num * __builtin_amdgcn_rcpf(den));
                             } else {
                                 r = cat_sum(sh_v[s][1 + side], K, l) / cat_sum(sh_v[s][0], K, l);
                             }
