@@ -22,7 +22,8 @@ def _gpu():
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("S,n,npat,K,seed", [(65, 17, 3, 4, 1), (100, 40, 1, 4, 2), (200, 20, 2, 2, 3),
-                                             (254, 8, 1, 1, 4), (120, 2, 1, 3, 5), (100, 300, 1, 1, 6)])
+                                             (254, 8, 1, 1, 4), (120, 2, 1, 3, 5), (100, 300, 1, 1, 6),
+                                             (80, 12, 2, 8, 7)])
 def test_matches_oracle(precision, S, n, npat, K, seed):
     wl = synth.make_workload("geo", n, npat, seed=seed, n_categories=K, n_states=S, unknown_frac=0.1)
     inst = make_instance(wl, precision, "every_node")

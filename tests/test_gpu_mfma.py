@@ -57,7 +57,7 @@ def test_odd_state_counts_fp64(S):
 
 
 @pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
-@pytest.mark.parametrize("K", [1, 6])
+@pytest.mark.parametrize("K", [1, 6, 8])
 def test_category_counts_mfma(K, precision):
     # K = 6 runs the 8-wave workgroups (one tile per wave), whose pending pre-order
     # partials also wait in LDS
