@@ -11,8 +11,8 @@ kernel (the traversal kernel, timed live with HIP events on the library's stream
 error against the FP64 oracle, synchronous-call latency percentiles, the oracle timed on a
 bounded sample of the same workload on the host cores, and the same measurements for the
 FP64 form and for the 64-taxon codon workload in FP32 / BF16 / FP16 / FP64 ("variants"),
-the rate-matrix gradient, the autograd modes, and the serving loop on 64 clients with Poisson
-arrivals ("serving").
+the rate-matrix gradient, the operation-level calls against one whole-tree call, the autograd
+modes, and the serving loop on 64 clients with Poisson arrivals ("serving").
 """
 from __future__ import annotations
 
@@ -373,6 +373,60 @@ def measure_eig(wl, precision: str, steps: int, warmup: int) -> dict:
             "error_vs_oracle": err}
 
 
+def measure_operation_level(wl, precision: str, steps: int) -> dict:
+    """One full evaluation through the operation-level calls (hp_update_matrices,
+    hp_update_post, hp_root_lnl, hp_pre_gradients with the library's own operation lists),
+    synchronous host in / host out, against the same evaluation as one hp_evaluate call on a
+    whole-tree instance: median ms per evaluation, and the error against the oracle."""
+    import numpy as np
+
+    from paper_2606_27607_amd import Instance, _lib, default_scaling
+
+    N, P, S, K = wl.n_tips, wl.n_patterns, wl.n_states, wl.n_categories
+    nb = 2 * N - 2
+    sc = default_scaling(S, precision)
+    post, pre = _lib.plan_tree(wl.tree.children, *sc)
+    op = Instance(N, P, S, K, precision=precision, scaling=sc[0], scale_period=sc[1],
+                  n_pre_partials=_lib.plan_pre_buffers(wl.tree.children))
+    op.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights)
+    whole = Instance(N, P, S, K, precision=precision, scaling=sc[0], scale_period=sc[1])
+    whole.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
+               children=wl.tree.children)
+    t = wl.t[:nb]
+    idx = np.arange(nb)
+
+    def op_eval():
+        op.update_matrices(idx, t)
+        op.update_post(post)
+        lnl = op.root_lnl(2 * N - 2)
+        return lnl, op.pre_gradients(pre, nb)
+
+    for _ in range(3):
+        lnl, g = op_eval()
+        whole.evaluate(t)
+    t_op, t_whole = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        op_eval()
+        t_op.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        whole.evaluate(t)
+        t_whole.append(time.perf_counter() - t0)
+    res = {"workload": wl.name, "precision": precision,
+           "ms_per_eval_operation_level": 1000 * float(np.median(t_op)),
+           "ms_per_eval_whole_tree": 1000 * float(np.median(t_whole))}
+    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{wl.name}.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+        gg = np.array(gold["grad"])
+        res["error_vs_oracle"] = {"lnl_rel": abs(lnl - gold["lnl"]) / abs(gold["lnl"]),
+                                  "grad_maxabs_over_maxabs": float(np.max(np.abs(g - gg)) / np.max(np.abs(gg)))}
+    op.close()
+    whole.close()
+    return res
+
+
 def measure_autograd(wl, precision: str, steps: int, period: int = 4) -> dict:
     """Forward + backward of BranchLengthLnL per mode (store / recompute / fused, and the
     checkpoint variant keeping every period-th level's partials), ms per step and post-order
@@ -642,6 +696,11 @@ def main():
         print("[bench] eigensystem path (phylogeography)", file=sys.stderr, flush=True)
         geo = synth.geo_workload()
         line["eigensystem_path"] = [measure_eig(geo, p, max(10, args.steps // 4), 3) for p in ("f64", "f32")]
+        print("[bench] operation-level calls", file=sys.stderr, flush=True)
+        line["operation_level"] = [
+            measure_operation_level(synth.config_workload("nuc128"), "f32", 20),
+            measure_operation_level(wls.get("codon64") or synth.config_workload("codon64"), "bf16", 20),
+            measure_operation_level(wls.get("codon64") or synth.config_workload("codon64"), "f32", 20)]
         print("[bench] autograd modes", file=sys.stderr, flush=True)
         line["autograd"] = [measure_autograd(synth.config_workload("nuc256"), "f32", 20),
                             measure_autograd(synth.config_workload("codon32"), "bf16", 20)]
