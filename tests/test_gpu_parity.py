@@ -344,3 +344,32 @@ def test_minimal_pre_buffers_bitwise_equal(kind, n, npat, precision):
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
     with pytest.raises(Exception):
         make_instance(wl, precision, *sc, n_pre_partials=need - 1)
+
+
+def test_op_level_calls_across_stream_switches():
+    """Operation-level calls whose uploads are staged without waiting for the device give
+    the same results when the caller's stream changes between them (the library completes
+    the previous stream's work first) as on one stream."""
+    import torch
+    wl = synth.make_workload("gtr", 30, 700, seed=13)
+    N = wl.n_tips
+    nb = 2 * N - 2
+    post, pre = post_ops(wl.tree.children, N), pre_ops(wl.tree.children, N)
+
+    def run(inst, streams):
+        out = []
+        for rep, s in enumerate(streams):
+            with torch.cuda.stream(s):
+                t = wl.t[:nb] * (1.0 + 0.01 * rep)
+                inst.update_matrices(np.arange(nb), t)
+                inst.update_post(post)
+                lnl = inst.root_lnl(2 * N - 2)
+                out.append((lnl, inst.pre_gradients(pre, nb)))
+        return out
+
+    announce("op-level calls across stream switches gtr30x700 f32")
+    one = run(make_instance(wl, "f32", "every_k", 4, tree=False), [torch.cuda.current_stream()] * 6)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    many = run(make_instance(wl, "f32", "every_k", 4, tree=False), [streams[i % 2] for i in range(6)])
+    for (l1, g1), (l2, g2) in zip(one, many):
+        assert l1 == l2 and np.array_equal(g1, g2)
