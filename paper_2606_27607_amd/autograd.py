@@ -20,7 +20,10 @@ gradient.  Modes:
 * ``"checkpoint"`` - ``inst`` is a :class:`~.checkpoint.Checkpointed` instance: forward keeps
                     the post-order partials of every m-th level only, and backward
                     recomputes the rest segment by segment (far fewer partial buffers, about
-                    one more post-order pass; the calls block on the host).
+                    one more post-order pass; the calls block on the host).  A backward pass
+                    whose forward state was overwritten (a later forward call, or a first
+                    backward pass) runs that forward pass again from its saved branch
+                    lengths.
 """
 from __future__ import annotations
 
@@ -39,6 +42,9 @@ class BranchLengthLnL(torch.autograd.Function):
         ctx.inst = inst
         if mode == "checkpoint":
             lnl = inst.lnl(t.cpu().numpy())
+            # the backward pass runs the forward pass again unless this token is still live
+            ctx.token = inst.forward_token
+            ctx.t_host = inst.last_t
             return torch.tensor(lnl, dtype=torch.float64, device=t.device)
         if mode == "fused":
             out = inst.evaluate_device(t, want_grad=True)
@@ -53,7 +59,8 @@ class BranchLengthLnL(torch.autograd.Function):
     def backward(ctx, grad_out):
         inst = ctx.inst
         if ctx.mode == "checkpoint":
-            g = torch.as_tensor(inst.gradients(), dtype=torch.float64, device=grad_out.device)
+            g = torch.as_tensor(inst.gradients(ctx.t_host, ctx.token), dtype=torch.float64,
+                                device=grad_out.device)
             return grad_out * g, None, None
         if ctx.mode == "fused":
             (g,) = ctx.saved_tensors

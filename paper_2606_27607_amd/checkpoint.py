@@ -144,10 +144,16 @@ class CheckpointPlan:
 
 class Checkpointed:
     """An instance evaluated through a CheckpointPlan: ``lnl(t)`` (forward, host lnL) then
-    ``gradients()`` (backward, host array of the 2N-2 branch gradients), once per forward
-    pass: the backward pass reuses the segment buffers, so it consumes the forward pass's
-    state.  ``create`` sizes a new instance for the plan (post-order buffers: the plan's
-    count, not N-1)."""
+    ``gradients()`` (backward, host array of the 2N-2 branch gradients).  ``create`` sizes a
+    new instance for the plan (post-order buffers: the plan's count, not N-1).
+
+    The backward pass reuses the segment buffers, so it consumes the state the forward pass
+    left.  Each forward pass returns with a token (``forward_token``: the instance's call
+    generation right after it); ``gradients(t, token)`` uses the buffers as they are only if
+    no other call has touched the instance since that forward pass and no backward pass has
+    consumed it.  Otherwise it first runs the forward pass again at ``t``, the branch
+    lengths whose gradient is wanted, so a second forward call or a repeated backward pass
+    never reads another evaluation's partials."""
 
     @classmethod
     def create(cls, n_tips, n_patterns, n_states, n_categories, children, period, *,
@@ -161,6 +167,7 @@ class Checkpointed:
 
     def load(self, tips, weights, V, Vinv, lam, pi, rates, cat_weights):
         self.inst.load(tips, weights, V, Vinv, lam, pi, rates, cat_weights)
+        self._live = None
         return self
 
     def __init__(self, inst, plan: CheckpointPlan):
@@ -171,16 +178,40 @@ class Checkpointed:
             raise ValueError(f"the instance needs n_partials >= {plan.n_post_buffers} and "
                              f"n_pre_partials >= {plan.n_pre_buffers}")
         self.inst, self.plan = inst, plan
+        self._last_t = None     # branch lengths of the last forward pass
+        self._live = None       # its token while its buffers are intact, else None
+
+    @property
+    def forward_token(self):
+        """Token of the last forward pass (None once a backward pass has consumed it)."""
+        return self._live
+
+    @property
+    def last_t(self):
+        return None if self._last_t is None else self._last_t.copy()
 
     def lnl(self, t) -> float:
         nb = 2 * self.plan.n_tips - 2
-        self.inst.update_matrices(np.arange(nb), np.asarray(t, dtype=np.float64)[:nb])
+        tt = np.array(np.asarray(t, dtype=np.float64)[:nb])
+        self.inst.update_matrices(np.arange(nb), tt)
         self.inst.update_post(self.plan.forward_ops)
-        return self.inst.root_lnl(self.plan.root_buf)
+        out = self.inst.root_lnl(self.plan.root_buf)
+        self._last_t = tt
+        self._live = self.inst.generation
+        return out
 
-    def gradients(self) -> np.ndarray:
-        """The 2N-2 branch gradients as a host array.  The pre-order batches add their
+    def gradients(self, t=None, token=None) -> np.ndarray:
+        """The 2N-2 branch gradients as a host array, at branch lengths ``t`` (default: those
+        of the last forward pass).  The forward pass is run again first unless ``token`` (by
+        default the last forward pass's) is still live.  The pre-order batches add their
         gradients into one device vector (stream-ordered), so the host waits once."""
+        if t is None:
+            if self._last_t is None:
+                raise RuntimeError("gradients() before any forward pass and without t")
+            t, token = self._last_t, self._live if token is None else token
+        if token is None or token != self._live or self.inst.generation != token:
+            self.lnl(t)
+        self._live = None       # the backward pass overwrites the segment buffers
         torch = self.inst.torch
         nb = 2 * self.plan.n_tips - 2
         acc = torch.zeros(nb, dtype=torch.float64, device=self.inst.device)

@@ -94,3 +94,93 @@ def test_period_beyond_height_keeps_only_the_root():
     recomputed = sum(len(ops) for kind, ops in plan.steps if kind == "post")
     assert recomputed == 40 - 2          # every internal node but the root, exactly once
 
+
+
+class _SymbolicInstance:
+    """Stands in for a library instance on the CPU: each post buffer holds (node, version of
+    the branch lengths it was computed from), the matrices hold a version, and every call
+    that is not read-only bumps ``generation`` as the binding does.  A pre-order batch
+    records, per gradient slot, the version of every partial it read."""
+
+    def __init__(self, n_tips, n_partials):
+        import torch
+        self.torch, self.device = torch, "cpu"
+        self.n_tips, self.generation = n_tips, 0
+        self.mats = None
+        self.post = {}
+        self.read_versions = {}
+
+    def update_matrices(self, idx, t):
+        self.generation += 1
+        self.mats = float(np.asarray(t)[0])       # the first branch length names the version
+
+    def update_post(self, ops):
+        self.generation += 1
+        for dest, c1, m1, c2, m2, _ in ops:
+            vs = {self.post[c][1] for c in (c1, c2) if c >= self.n_tips} | {self.mats}
+            assert len(vs) == 1, "a partial combined children of different evaluations"
+            self.post[int(dest)] = (int(m1), self.mats)
+
+    def root_lnl(self, root_buf):
+        self.generation += 1
+        return self.post[root_buf][1]
+
+    def pre_gradients_device(self, ops, acc):
+        self.generation += 1
+        for pp, c1, m1, q1, g1, c2, m2, q2, g2 in ops:
+            for c, g in ((c1, g1), (c2, g2)):
+                v = self.post[c][1] if c >= self.n_tips else self.mats
+                self.read_versions.setdefault(int(g), set()).add(v)
+                acc[int(g)] += v
+        return acc
+
+
+def _symbolic_checkpointed(n=40, period=3):
+    from paper_2606_27607_amd.checkpoint import Checkpointed
+    yule = synth.trees.yule_tree(n, np.random.default_rng(11)).children
+    plan = CheckpointPlan(yule, period)
+    inst = _SymbolicInstance(n, plan.n_post_buffers)
+    inst.desc = type("D", (), {"n_partials": plan.n_post_buffers, "n_pre_partials": plan.n_pre_buffers})
+    return Checkpointed(inst, plan), inst, 2 * n - 2
+
+
+def test_backward_after_a_second_forward_reads_its_own_evaluation():
+    """Two forward passes, then the backward pass of the first: it must not read the second
+    evaluation's partials or matrices (it runs the first forward pass again)."""
+    ck, inst, nb = _symbolic_checkpointed()
+    t1, t2 = np.full(nb, 0.1), np.full(nb, 0.2)
+    ck.lnl(t1)
+    tok1, saved1 = ck.forward_token, ck.last_t
+    ck.lnl(t2)
+    g = ck.gradients(saved1, tok1)
+    assert all(v == {0.1} for v in inst.read_versions.values())
+    assert np.allclose(g, 0.1)                          # each slot read once, at version 0.1
+
+
+def test_repeated_backward_reruns_the_forward_pass():
+    """A backward pass consumes the forward state: a second backward pass of the same
+    forward call (retain_graph) runs the forward pass again, and gives the same values."""
+    ck, inst, nb = _symbolic_checkpointed(period=2)
+    ck.lnl(np.full(nb, 0.3))
+    tok, saved = ck.forward_token, ck.last_t
+    g1 = ck.gradients(saved, tok)
+    assert ck.forward_token is None
+    gen = inst.generation
+    g2 = ck.gradients(saved, tok)
+    assert inst.generation > gen + 3                    # forward (3 calls) + backward ran
+    assert np.array_equal(g1, g2)
+    # with the state live, no forward pass runs again
+    ck.lnl(np.full(nb, 0.4))
+    gen = inst.generation
+    ck.gradients()
+    n_backward = len(ck.plan.steps)
+    assert inst.generation == gen + n_backward
+
+
+def test_intervening_call_invalidates_the_forward_state():
+    ck, inst, nb = _symbolic_checkpointed()
+    ck.lnl(np.full(nb, 0.5))
+    tok, saved = ck.forward_token, ck.last_t
+    inst.update_matrices(np.arange(nb), np.full(nb, 0.9))   # any other use of the instance
+    ck.gradients(saved, tok)
+    assert all(v == {0.5} for v in inst.read_versions.values())
