@@ -44,6 +44,14 @@ def algorithmic_bytes(n_tips: int, n_patterns: int, n_states: int, n_cat: int, e
     return 5.0 * (n_tips - 2) * E * elem + 2.0 * n_tips * n_patterns
 
 
+def floor_bytes(n_tips: int, n_patterns: int, n_states: int, n_cat: int, elem: int) -> float:
+    """The tile-resident floor: the bytes a full evaluation must move when every non-root
+    internal node's post-order partial is written once and read once (pre-order partials
+    never leave the chip) - 2 (N-2) E b - plus the tip states read once in each pass."""
+    E = n_patterns * n_cat * n_states
+    return 2.0 * (n_tips - 2) * E * elem + 2.0 * n_tips * n_patterns
+
+
 def algorithmic_flops(n_tips: int, n_patterns: int, n_states: int, n_cat: int) -> float:
     """Flops of one full evaluation: one matrix-vector product (2 S^2) per pattern and
     category for every internal child edge in the post-order pass, and three (recomputed
@@ -96,10 +104,15 @@ def _oracle_chunk(args) -> float:
         return float(oracle.lnl_and_grad(children, n_tips, t, Q, pi, rates, cat_w, tips, w)[0])
 
 
-def cpu_baseline(wl, sample_patterns: int, max_procs: int = 16):
+# patterns of each configuration the oracle is timed on (about 1-5 s of one host core each)
+CPU_SAMPLE = {"nuc8": 1000, "nuc128": 60000, "codon64": 2000, "nuc256": 10000, "codon32": 5000}
+
+
+def cpu_baseline(wl, sample_patterns: int, max_procs: int = 16, all_cores: bool = True, repeats: int = 1):
     """The FP64 oracle on the first `sample_patterns` patterns, scaled to evals/s of the
-    full workload: on one thread (the reported value), and on all host cores as a pool of
-    processes over pattern chunks (patterns are independent), one BLAS thread each."""
+    full workload: on one thread (the reported value; the median of `repeats` runs), and on
+    all host cores as a pool of processes over pattern chunks (patterns are independent),
+    one BLAS thread each."""
     import multiprocessing as mp
 
     import numpy as np
@@ -108,18 +121,24 @@ def cpu_baseline(wl, sample_patterns: int, max_procs: int = 16):
     import oracle
     tips = wl.tips[:, :sample_patterns]
     w = wl.weights[:sample_patterns]
+    runs = []
     with threadpool_limits(1):
-        t0 = time.perf_counter()
-        oracle.lnl_and_grad(wl.tree.children, wl.n_tips, wl.t, wl.Q, wl.pi, wl.rates,
-                            wl.cat_weights, tips, w)
-        dt = time.perf_counter() - t0
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            oracle.lnl_and_grad(wl.tree.children, wl.n_tips, wl.t, wl.Q, wl.pi, wl.rates,
+                                wl.cat_weights, tips, w)
+            runs.append(time.perf_counter() - t0)
+    dt = sorted(runs)[len(runs) // 2]
     full = dt * wl.n_patterns / sample_patterns
     affinity = len(os.sched_getaffinity(0))
     res = {"value": 1.0 / full, "unit": "evals/s", "cores": 1, "kind": "oracle",
-           "sample": f"first {sample_patterns} of {wl.n_patterns} patterns of the same workload, "
+           "sample": f"first {sample_patterns} of {wl.n_patterns} patterns of {wl.name}, "
                      f"lnL + all {2 * wl.n_tips - 2} gradients, FP64 NumPy/SciPy, 1 thread; "
-                     f"{dt:.1f} s measured, scaled by patterns",
+                     f"{dt:.3f} s measured" + (f" (median of {repeats})" if repeats > 1 else "")
+                     + ", scaled by patterns",
            "seconds_per_eval": full, "host_cpus": affinity, "os_cpu_count": os.cpu_count()}
+    if not all_cores:
+        return res
     # all cores: the same sample in one chunk per process (spawned: this process has used
     # the GPU), median of three timed passes after a warm-up pass
     procs = max(1, min(affinity, max_procs))
@@ -204,10 +223,14 @@ def measure(wl, precision: str, steps: int, warmup: int, latency_samples: int) -
     trav_ms = prof["traversal"][0] / max(1, prof["traversal"][1])
     alg = algorithmic_bytes(N, P, S, K, ELEM[precision])
     gbs = alg / (trav_ms * 1e-3) / 1e9
+    floor = floor_bytes(N, P, S, K, ELEM[precision])
     traffic = measured_traffic(KERNEL_SOURCES[small], wl.name, precision)
+    # the same time against the tile-resident floor, and against the HBM bytes the counters saw
+    fracs = {"floor_bytes": floor, "floor_frac": floor / (trav_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "counter_frac": (traffic / (trav_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None}
     if small:
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, **fracs,
                 "kernel": "walk_small (fused post-order + root + pre-order + gradients)",
                 "kernel_ms": trav_ms, "algorithmic_bytes": alg}
     else:
@@ -218,7 +241,7 @@ def measure(wl, precision: str, steps: int, warmup: int, latency_samples: int) -
                 "frac": tf / peak, "traffic": traffic,
                 "kernel": f"walk_mfma<{precision}> (fused post-order + root + pre-order + gradients)",
                 "kernel_ms": trav_ms, "algorithmic_flops": fl, "algorithmic_bytes": alg,
-                "hbm_GBs_algorithmic": gbs, "hbm_frac_algorithmic": gbs / HBM_PEAK_GBS}
+                "hbm_GBs_algorithmic": gbs, "hbm_frac_algorithmic": gbs / HBM_PEAK_GBS, **fracs}
 
     lat = []
     for i in range(latency_samples):
@@ -599,6 +622,34 @@ def serving_bench(inputs, loads=(0.5, 0.8, 1.0), seed: int = 20260055) -> dict:
             "arrivals": "Poisson, rate = load x isolated capacity, requests in random order"}
 
 
+def serving_cpu_baseline() -> dict:
+    """The FP64 oracle on the serving sample (per state space the smallest client and the one
+    of median size, first request), one host thread, on a prefix of each client's patterns
+    (at most 4,000 / 1,000 / 100 for 4 / 20 / 61 states) scaled to the whole request."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    import synth
+    per = {}
+    for c in synth.serving_oracle_sample():
+        wl = synth.serving_workload(c)
+        t = synth.serving_requests(wl, c)[0]
+        import numpy as np
+        n = min(wl.n_patterns, {4: 4000, 20: 1000, 61: 100}[wl.n_states])
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            oracle.lnl_and_grad(wl.tree.children, wl.n_tips, np.r_[t, 0.0], wl.Q, wl.pi, wl.rates, wl.cat_weights,
+                                wl.tips[:, :n], wl.weights[:n])
+            dt = time.perf_counter() - t0
+        per[str(c)] = {"states": wl.n_states, "taxa": wl.n_tips, "patterns": wl.n_patterns,
+                       "sample_patterns": n, "seconds_per_request": dt * wl.n_patterns / n}
+    total = sum(v["seconds_per_request"] for v in per.values())
+    return {"value": len(per) / total, "unit": "requests/s", "cores": 1, "kind": "oracle",
+            "sample": "first request of the smallest and the median client per state space "
+                      "(lnL + all branch gradients), pattern prefixes scaled to the whole request",
+            "clients": per}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -667,6 +718,7 @@ def main():
             "error_vs_oracle": head["error_vs_oracle"], "latency_ms": head["latency_ms"]}
     if not args.no_variants:
         variants = []
+        baselined = {args.workload}
         # the 8-taxon FP64 case is latency-bound: its line is read for the per-call latency
         plan = [("nuc8", "f64")]
         plan += [("nuc128", "f64")] if args.workload == "nuc128" else []
@@ -679,6 +731,13 @@ def main():
             if name not in wls:
                 wls[name] = synth.config_workload(name)
             variants.append(measure(wls[name], prec, max(10, args.steps // 2), 3, 200 if name == "nuc8" else 10))
+            if not args.no_cpu_baseline and name not in baselined and name in CPU_SAMPLE:
+                # the oracle on this configuration (once per workload), beside its GPU line
+                baselined.add(name)
+                print(f"[bench] cpu baseline (oracle) {name}", file=sys.stderr, flush=True)
+                variants[-1]["cpu_baseline"] = cpu_baseline(
+                    wls[name], min(CPU_SAMPLE[name], wls[name].n_patterns), all_cores=name != "nuc8",
+                    repeats=21 if name == "nuc8" else 1)
         line["variants"] = variants
         by = {(v["config"]["taxa"], v["dtype"]): v for v in variants}
         c32 = by.get((64, "f32"))
@@ -704,6 +763,10 @@ def main():
         print("[bench] autograd modes", file=sys.stderr, flush=True)
         line["autograd"] = [measure_autograd(synth.config_workload("nuc256"), "f32", 20),
                             measure_autograd(synth.config_workload("codon32"), "bf16", 20)]
+        if not args.no_cpu_baseline:
+            for rec, name in zip(line["autograd"], ("nuc256", "codon32")):
+                print(f"[bench] cpu baseline (oracle) {name}", file=sys.stderr, flush=True)
+                rec["cpu_baseline"] = cpu_baseline(synth.config_workload(name), CPU_SAMPLE[name])
     if serving_data is not None:
         print("[bench] serving", file=sys.stderr, flush=True)
         try:
@@ -714,6 +777,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, wl.n_patterns))
+        if "serving" in line and "error" not in line["serving"]:
+            print("[bench] cpu baseline (oracle) serving sample", file=sys.stderr, flush=True)
+            line["serving"]["cpu_baseline"] = serving_cpu_baseline()
     print(json.dumps(line), flush=True)
 
 

@@ -68,6 +68,9 @@ extern "C" {
 #define HP_PREC_F32   1  /* partials and arithmetic in FP32 (the plain single-precision form)  */
 #define HP_PREC_BF16  2  /* partials stored in BF16, partials x P(t) on MFMA, FP32 accumulation */
 #define HP_PREC_F16   3  /* partials stored in FP16, partials x P(t) on MFMA, FP32 accumulation */
+#define HP_PREC_BF16X3 4 /* partials stored in FP32, partials x P(t) on the BF16 MFMA with both
+                            operands split into hi + lo BF16 parts (three products per step:
+                            hi.hi + hi.lo + lo.hi, ~2^-17 relative), FP32 accumulation     */
 
 /* ---------------------------------------------------------------- rescaling policies
  * Rescaling multiplies a node's partials for one pattern by 2^-e, e being the
@@ -164,9 +167,11 @@ int hp_set_tip_states(hp_instance* inst, int tip, const uint8_t* states, int on_
 int hp_set_pattern_weights(hp_instance* inst, const double* weights);
 /* Stationary frequencies of slot idx (host, FP64, S values, > 0, summing to 1 +- 1e-9). */
 int hp_set_frequencies(hp_instance* inst, int idx, const double* pi);
-/* Rate-category rates r_k >= 0 and weights w_k >= 0 (host FP64, K values each). */
+/* Rate-category rates r_k >= 0 (host FP64, K values), shared by every matrix and slot. */
 int hp_set_category_rates(hp_instance* inst, const double* rates);
-int hp_set_category_weights(hp_instance* inst, const double* weights);
+/* Category weights w_k >= 0 of slot idx (host FP64, K values; n_eigen slots, each 1/K at
+ * creation).  The whole-tree calls use slot 0; the root and gradient calls name theirs. */
+int hp_set_category_weights(hp_instance* inst, int idx, const double* weights);
 /* Eigensystem of slot idx: row-major S x S V and Vinv with Q = V diag(lam) Vinv (host FP64).
  * The library also forms Q itself in FP64, for the gradient. */
 int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv,
@@ -185,31 +190,46 @@ int hp_update_matrices(hp_instance* inst, int eigen_idx, const int32_t* mat_idx,
 /* Post-order partial updates, in list order (children must be computed before use). */
 int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count);
 
-/* Root integration of post buffer root_buf with frequency slot freq_idx:
- *   l_p = ln(sum_k w_k sum_x pi_x post[k,p,x]) + E_p ln 2 ,  lnL = sum_p c_p l_p  (FP64).
+/* Root integration (the likelihood at the root of Felsenstein's pruning; Introduction) of
+ * post buffer root_buf with frequency slot freq_idx and category-weight slot catw_idx:
+ *   l_p = ln(sum_k w_k sum_x pi_x post[k,p,x]) + E_p ln 2 ,  lnL = sum_p c_p l_p  (FP64),
+ * E_p being the cumulative rescaling exponent the buffer carries for its subtree (every
+ * post buffer holds its own, in place of separate scale buffers).
  * Blocking: writes *out_lnl and, if out_site_lnl != NULL, n_patterns values (host).
  * Returns HP_ERR_NUMERIC (and lnL = -inf) if some weighted site likelihood is 0 or
  * not finite. */
-int hp_root_lnl(hp_instance* inst, int root_buf, int freq_idx, double* out_lnl,
+int hp_root_lnl(hp_instance* inst, int root_buf, int freq_idx, int catw_idx, double* out_lnl,
                 double* out_site_lnl);
+/* The same, stream-ordered into device memory: d_lnl (1 FP64) and, if d_site_lnl != NULL,
+ * n_patterns FP64 site log-likelihoods.  Nothing waits for the device; a zero site
+ * likelihood makes lnL -inf and raises the status word read by hp_status (HP_ERR_NUMERIC). */
+int hp_root_lnl_device(hp_instance* inst, int root_buf, int freq_idx, int catw_idx, double* d_lnl,
+                       double* d_site_lnl);
 
-/* Pre-order partial updates (no gradients), in list order (parents before children). */
+/* Pre-order partial updates (no gradients), in list order (parents before children):
+ * pre_c = P_c^T (pre_n o P_s post_s) for child c of n with sibling s, pre_root = pi (the
+ * pre-order traversal that complements the post-order one; Key Improvements, Algorithmic
+ * advances).  Rescaled per pattern when the instance rescales; those exponents cancel in
+ * the gradient and are not kept. */
 int hp_update_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx);
 
-/* Pre-order partial updates fused with the branch-length gradients of the model whose
- * rate matrix comes from eigen slot eigen_idx: for every child c with gradX >= 0,
+/* Pre-order partial updates fused with the branch-length gradients (the sandwich of a
+ * pre-order partial, the rate matrix and a post-order partial, evaluated for every branch
+ * in one pre-order traversal; Key Improvements, Algorithmic advances; Discussion) of the
+ * model whose rate matrix comes from eigen slot eigen_idx, with category-weight slot
+ * catw_idx: for every child c with gradX >= 0,
  *   out_grad[gradX] = sum_p c_p [sum_k w_k r_k pre_c^T Q post_c] / [sum_k w_k pre_c^T post_c]
  * Blocking; out_grad is host memory of n_grad FP64 values, slots not named by the list
  * are set to 0. */
 int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx,
-                     int eigen_idx, double* out_grad, int n_grad);
+                     int catw_idx, int eigen_idx, double* out_grad, int n_grad);
 
 /* Stream-ordered form of hp_pre_gradients: d_grad is device memory of n_grad FP64 values
  * and the list's gradients are added to it (slots the list does not name gain +0), so the
  * batches of one backward pass accumulate into one vector.  Nothing waits for the device;
  * the operation list is copied before return. */
 int hp_pre_gradients_device(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx,
-                            int eigen_idx, double* d_grad, int n_grad);
+                            int catw_idx, int eigen_idx, double* d_grad, int n_grad);
 
 /* ---------------------------------------------------------------- whole-tree evaluation */
 

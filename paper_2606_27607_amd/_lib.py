@@ -27,7 +27,7 @@ ERROR_NAMES = {
     HP_ERR_STATE: "HP_ERR_STATE", HP_ERR_DEVICE: "HP_ERR_DEVICE", HP_ERR_NUMERIC: "HP_ERR_NUMERIC",
 }
 
-PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4}
 SCALINGS = {"none": 0, "every_node": 1, "every_k": 2}
 
 
@@ -73,14 +73,15 @@ SIGNATURES = {
     "hp_set_pattern_weights": [_P, _P],
     "hp_set_frequencies": [_P, _I, _P],
     "hp_set_category_rates": [_P, _P],
-    "hp_set_category_weights": [_P, _P],
+    "hp_set_category_weights": [_P, _I, _P],
     "hp_set_eigen": [_P, _I, _P, _P, _P],
     "hp_update_matrices": [_P, _I, _P, _P, _I],
     "hp_update_post": [_P, _P, _I],
-    "hp_root_lnl": [_P, _I, _I, _P, _P],
+    "hp_root_lnl": [_P, _I, _I, _I, _P, _P],
+    "hp_root_lnl_device": [_P, _I, _I, _I, _P, _P],
     "hp_update_pre": [_P, _P, _I, _I],
-    "hp_pre_gradients": [_P, _P, _I, _I, _I, _P, _I],
-    "hp_pre_gradients_device": [_P, _P, _I, _I, _I, _P, _I],
+    "hp_pre_gradients": [_P, _P, _I, _I, _I, _I, _P, _I],
+    "hp_pre_gradients_device": [_P, _P, _I, _I, _I, _I, _P, _I],
     "hp_set_tree": [_P, _P],
     "hp_plan_tree": [_I, _P, _I, _I, _P, _P],
     "hp_plan_pre_buffers": [_I, _P, ctypes.POINTER(ctypes.c_int)],
@@ -159,3 +160,4 @@ def plan_pre_buffers(children) -> int:
     check(lib, lib.hp_plan_pre_buffers((ch.shape[0] + 1) // 2, ctypes.c_void_p(ch.ctypes.data),
                                        ctypes.byref(n)))
     return n.value
+

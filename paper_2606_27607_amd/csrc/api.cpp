@@ -55,6 +55,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 const char* const kEigWholeTreeOnly =
     "more than 64 states: only whole-tree evaluation (hp_set_tree, hp_evaluate[_device]) is supported";
 
+}  // namespace
+
+namespace hp {
+int fail_global(int code, const std::string& msg) { return fail(nullptr, code, msg); }
+
 int check_desc(const hp_desc* d) {
     if (!d) return fail(nullptr, HP_ERR_ARG, "descriptor is NULL");
     if (d->n_tips < 2) return fail(nullptr, HP_ERR_ARG, "n_tips must be >= 2");
@@ -66,16 +71,16 @@ int check_desc(const hp_desc* d) {
     if (d->n_partials < 1 || d->n_matrices < 1 || d->n_eigen < 1)
         return fail(nullptr, HP_ERR_ARG, "n_partials, n_matrices and n_eigen must be >= 1");
     if (d->n_pre_partials < 0) return fail(nullptr, HP_ERR_ARG, "n_pre_partials must be >= 0");
-    if (d->precision < HP_PREC_F64 || d->precision > HP_PREC_F16)
+    if (d->precision < HP_PREC_F64 || d->precision > HP_PREC_BF16X3)
         return fail(nullptr, HP_ERR_ARG, "unknown precision");
     if (d->scaling < HP_SCALE_NONE || d->scaling > HP_SCALE_EVERY_K_LEVELS)
         return fail(nullptr, HP_ERR_ARG, "unknown scaling policy");
     if (d->scaling == HP_SCALE_EVERY_K_LEVELS && d->scale_period < 1)
         return fail(nullptr, HP_ERR_ARG, "scale_period must be >= 1");
-    const bool lowp = d->precision == HP_PREC_BF16 || d->precision == HP_PREC_F16;
+    const bool lowp = hp::mfma16(d->precision);
     if (lowp && d->n_states <= 4)
         return fail(nullptr, HP_ERR_UNSUPPORTED,
-                    "BF16/FP16 matrix-core partials are for S > 4 (amino-acid and codon models)");
+                    "BF16/FP16 matrix-core products are for S > 4 (amino-acid and codon models)");
     if (lowp && d->n_states > hp::kMaxStates)
         return fail(nullptr, HP_ERR_UNSUPPORTED, "more than 64 states run in FP64 or FP32");
     // guard the int32 index arithmetic inside kernels
@@ -84,6 +89,10 @@ int check_desc(const hp_desc* d) {
         return fail(nullptr, HP_ERR_UNSUPPORTED, "n_patterns * n_categories too large for one instance");
     return HP_OK;
 }
+}  // namespace hp
+
+namespace {
+using hp::check_desc;
 
 int max_grad_slots(const hp_desc& d) {
     return std::max(d.n_matrices, 2 * d.n_tips - 2);
@@ -135,7 +144,7 @@ int compute_layout_eig(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* el
     l.Qc = take(ne * S_pad * S_pad * elem);
     l.freq_c = take(ne * S_pad * elem);
     l.freq_d = take(ne * S_pad * 8);
-    l.cat_d = take(2 * kMaxCategories * 8);
+    l.cat_d = take((1 + ne) * kMaxCategories * 8);
     l.t_stage = take(nbr * 8);
     l.idx_stage = take(nbr * 4);
     l.eig_lists = take((size_t)8 * N * 4);
@@ -155,7 +164,7 @@ int compute_layout_eig(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* el
 int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_out, Layout* L) {
     if (d.n_states > kMaxStates) return compute_layout_eig(d, S_pad_out, P_pad_out, elem_out, L);
     const int S = d.n_states, K = d.n_categories;
-    const bool lowp = d.precision == HP_PREC_BF16 || d.precision == HP_PREC_F16;
+    const bool lowp = mfma16(d.precision);
     int S_pad;
     if (S <= 4) S_pad = 4;                 // vector-ALU path
     else S_pad = S <= 32 ? 32 : 64;        // matrix-core path: MFMA tiles of 16 states
@@ -163,7 +172,7 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     // the matrix-core path to whole groups of one, two or three 16-pattern tiles
     const int pad = S_pad == 4 ? kWave * kMaxSmallPpl : 192;
     const int P_pad = (d.n_patterns + pad - 1) / pad * pad;
-    const int elem = d.precision == HP_PREC_F64 ? 8 : d.precision == HP_PREC_F32 ? 4 : 2;
+    const int elem = d.precision == HP_PREC_F64 ? 8 : (d.precision == HP_PREC_BF16 || d.precision == HP_PREC_F16) ? 2 : 4;
     const int celem = d.precision == HP_PREC_F64 ? 8 : 4;  // matrices / Q / freqs: FP64 or FP32
     const size_t np = (size_t)d.n_partials, nm = (size_t)d.n_matrices, ne = (size_t)d.n_eigen;
     Layout l{};
@@ -202,7 +211,7 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     if (lowp) l.Q16 = take(ne * S_pad * S_pad * 2 * 2);
     l.freq_c = take(ne * S_pad * celem);
     l.freq_d = take(ne * S_pad * 8);
-    l.cat_d = take(2 * kMaxCategories * 8);
+    l.cat_d = take((1 + ne) * kMaxCategories * 8);
     l.t_stage = take(nm * 8);
     l.idx_stage = take(nm * 4);
     l.ops_stage = take((size_t)max_ops(d) * kPreOpInts * 4);
@@ -276,12 +285,15 @@ int upload_compute(Instance* I, size_t off, const std::vector<double>& v) {
     return upload(I, I->ws + off, buf.data(), buf.size());
 }
 
+// Read and clear the device status word in one atomic exchange on the instance's stream, so
+// that a bit raised meanwhile by work on another stream (batched launches) is kept for the
+// next read instead of being cleared unseen.
 int read_status(Instance* I, int32_t* out) {
-    HP_HIP(I, hipMemcpyAsync(I->host_status, I->at<int32_t>(I->L.status), 4, hipMemcpyDeviceToHost,
-                             I->stream));
+    int32_t* st = I->at<int32_t>(I->L.status);
+    HP_HIP(I, hp::launch_status_take(*I, st, st + 2));
+    HP_HIP(I, hipMemcpyAsync(I->host_status, st + 2, 4, hipMemcpyDeviceToHost, I->stream));
     HP_HIP(I, hipStreamSynchronize(I->stream));
     *out = *I->host_status;
-    if (*out) HP_HIP(I, hp::launch_fill_i32(*I, I->at<int32_t>(I->L.status), 0, 1));
     return HP_OK;
 }
 
@@ -347,7 +359,7 @@ int check_mat(Instance* I, int m) {
 
 }  // namespace
 
-namespace {
+namespace hp {
 
 // Patterns per lane of the 4-state traversal.  Every workgroup walks the whole tree, so a
 // launch is a few rounds of resident workgroups and a round costs nearly a full walk even
@@ -414,7 +426,14 @@ void choose_mfma_blocks(Instance* I) {
     I->L.n_blocks = I->n_blocks = (int)nb;
 }
 
-}  // namespace
+void choose_launch_shape(Instance* I) {
+    if (I->S_pad == 4) choose_small_tile(I);
+    else if (!I->eig) choose_mfma_blocks(I);
+}
+
+}  // namespace hp
+
+using hp::op_blocks;
 
 // ===================================================================== C ABI
 
@@ -449,8 +468,7 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
     }
     I->n_blocks = I->L.n_blocks;
     I->eig = desc->n_states > hp::kMaxStates;
-    if (I->S_pad == 4) choose_small_tile(I);
-    else if (!I->eig) choose_mfma_blocks(I);
+    hp::choose_launch_shape(I);
     I->ws = static_cast<uint8_t*>(dev_workspace);
     I->ws_bytes = workspace_bytes;
     I->stream = static_cast<hipStream_t>(hip_stream);
@@ -491,10 +509,10 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
                             I->P_pad - desc->n_patterns) ||
         hp::launch_fill_i32(*I, I->at<int32_t>(I->L.status), 0, 16))
         return cleanup(fail(I, HP_ERR_DEVICE, "initialising the workspace failed"));
-    std::vector<double> cat(2 * hp::kMaxCategories, 0.0);
+    std::vector<double> cat((size_t)(1 + desc->n_eigen) * hp::kMaxCategories, 0.0);
     for (int k = 0; k < K; ++k) {
         cat[k] = 1.0;
-        cat[hp::kMaxCategories + k] = 1.0 / K;
+        for (int i = 0; i < desc->n_eigen; ++i) cat[(size_t)(1 + i) * hp::kMaxCategories + k] = 1.0 / K;
     }
     if (upload(I, I->ws + I->L.cat_d, cat.data(), cat.size() * 8)) return cleanup(HP_ERR_DEVICE);
     *out = reinterpret_cast<hp_instance*>(I);
@@ -607,6 +625,7 @@ static int set_cat(hp_instance* inst, const double* v, int which) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
     if (!v) return fail(I, HP_ERR_ARG, "category array is NULL");
+    if (which < 0 || which > I->d.n_eigen) return fail(I, HP_ERR_INDEX, "category-weight slot out of range");
     for (int k = 0; k < I->d.n_categories; ++k)
         if (!(v[k] >= 0.0) || !std::isfinite(v[k])) return fail(I, HP_ERR_VALUE, "category value < 0 or not finite");
     DeviceGuard g(I->d.device);
@@ -615,7 +634,9 @@ static int set_cat(hp_instance* inst, const double* v, int which) {
 }
 
 int hp_set_category_rates(hp_instance* inst, const double* r) { return set_cat(inst, r, 0); }
-int hp_set_category_weights(hp_instance* inst, const double* w) { return set_cat(inst, w, 1); }
+int hp_set_category_weights(hp_instance* inst, int idx, const double* w) {
+    return set_cat(inst, w, idx < 0 ? -1 : 1 + idx);
+}
 
 int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv, const double* lam) {
     if (!inst) return HP_ERR_ARG;
@@ -665,7 +686,7 @@ int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv
         const size_t n = Q.size();
         std::vector<uint16_t> hi(n), lo(n, 0);
         for (size_t i = 0; i < n; ++i) {
-            if (I->d.precision == HP_PREC_BF16) {
+            if (hp::bf16_split(I->d.precision)) {
                 hi[i] = hp::to_bf16_bits(Q[i]);
                 lo[i] = hp::to_bf16_bits(Q[i] - hp::bf16_bits_to_double(hi[i]));
             } else {
@@ -733,23 +754,48 @@ int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count) {
     return HP_OK;
 }
 
-int hp_root_lnl(hp_instance* inst, int root_buf, int freq_idx, double* out_lnl, double* out_site) {
-    if (!inst) return HP_ERR_ARG;
-    auto* I = reinterpret_cast<Instance*>(inst);
+// Root integration of a post buffer into device memory: lnL to d_lnl (FP64) and, if d_site is
+// not NULL, the n_patterns site log-likelihoods to d_site.  Stream-ordered.
+static int enqueue_root(Instance* I, int root_buf, int freq_idx, int catw_idx, double* d_lnl, double* d_site) {
     if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, kEigWholeTreeOnly);
-    if (!out_lnl) return fail(I, HP_ERR_ARG, "out_lnl is NULL");
     int rc = check_post_buf(I, root_buf, "root_buf");
     if (rc) return rc;
     if (freq_idx < 0 || freq_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "frequency slot out of range");
     if (!I->freq_set[freq_idx]) return fail(I, HP_ERR_STATE, "frequencies not set");
-    DeviceGuard g(I->d.device);
+    if (catw_idx < 0 || catw_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "category-weight slot out of range");
     hp::WalkArgs a;
     a.mode = hp::kRootBuf;
     a.root_buf = root_buf;
     a.freq_idx = freq_idx;
-    a.site = out_site ? I->at<double>(I->L.site) : nullptr;
+    a.catw_idx = catw_idx;
+    // the kernels write a site value for every padded pattern: into the workspace's row,
+    // then the first n_patterns are copied out
+    double* site = I->at<double>(I->L.site);
+    a.site = d_site ? site : nullptr;
     HP_HIP(I, HP_WALK(*I, a));
-    HP_HIP(I, HP_REDUCE(*I, 1, I->at<double>(I->L.results), 0, false, op_blocks(I)));
+    HP_HIP(I, HP_REDUCE(*I, 1, d_lnl, 0, false, op_blocks(I)));
+    if (d_site && d_site != site)
+        HP_HIP(I, hipMemcpyAsync(d_site, site, (size_t)I->d.n_patterns * 8, hipMemcpyDeviceToDevice, I->stream));
+    return HP_OK;
+}
+
+int hp_root_lnl_device(hp_instance* inst, int root_buf, int freq_idx, int catw_idx, double* d_lnl,
+                       double* d_site) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!d_lnl) return fail(I, HP_ERR_ARG, "d_lnl is NULL");
+    DeviceGuard g(I->d.device);
+    return enqueue_root(I, root_buf, freq_idx, catw_idx, d_lnl, d_site);
+}
+
+int hp_root_lnl(hp_instance* inst, int root_buf, int freq_idx, int catw_idx, double* out_lnl, double* out_site) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!out_lnl) return fail(I, HP_ERR_ARG, "out_lnl is NULL");
+    DeviceGuard g(I->d.device);
+    int rc = enqueue_root(I, root_buf, freq_idx, catw_idx, I->at<double>(I->L.results),
+                          out_site ? I->at<double>(I->L.site) : nullptr);
+    if (rc) return rc;
     HP_HIP(I, hipMemcpyAsync(I->host_out, I->at<double>(I->L.results), 8, hipMemcpyDeviceToHost, I->stream));
     if (out_site)
         HP_HIP(I, hipMemcpyAsync(out_site, I->at<double>(I->L.site), (size_t)I->d.n_patterns * 8,
@@ -793,7 +839,7 @@ static int check_pre_ops(Instance* I, const hp_pre_op* ops, int count, int n_gra
 
 // grad: gradients too, into host out_grad (blocking) or, with on_device, added to device
 // out_grad (stream-ordered)
-static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int eigen_idx,
+static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int catw_idx, int eigen_idx,
                    double* out_grad, int n_grad, bool grad, bool on_device = false) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
@@ -804,6 +850,7 @@ static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_
     if (!I->freq_set[freq_idx]) return fail(I, HP_ERR_STATE, "frequencies not set");
     if (grad) {
         if (!out_grad) return fail(I, HP_ERR_ARG, "out_grad is NULL");
+        if (catw_idx < 0 || catw_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "category-weight slot out of range");
         if (n_grad < 0 || n_grad > max_grad_slots(I->d)) return fail(I, HP_ERR_ARG, "bad n_grad");
         if (eigen_idx < 0 || eigen_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "eigen slot out of range");
         if (!I->eigen_set[eigen_idx]) return fail(I, HP_ERR_STATE, "eigensystem not set");
@@ -820,6 +867,7 @@ static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_
     a.pre_ops = I->at<int32_t>(I->L.ops_stage);
     a.n_pre = count;
     a.freq_idx = freq_idx;
+    a.catw_idx = grad ? catw_idx : 0;
     a.eigen_idx = grad ? eigen_idx : 0;
     a.n_grad = grad ? n_grad : 0;
     HP_HIP(I, HP_WALK(*I, a));
@@ -838,17 +886,17 @@ static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_
 }
 
 int hp_update_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx) {
-    return run_pre(inst, ops, count, freq_idx, 0, nullptr, 0, false);
+    return run_pre(inst, ops, count, freq_idx, 0, 0, nullptr, 0, false);
 }
 
-int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int eigen_idx,
+int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int catw_idx, int eigen_idx,
                      double* out_grad, int n_grad) {
-    return run_pre(inst, ops, count, freq_idx, eigen_idx, out_grad, n_grad, true);
+    return run_pre(inst, ops, count, freq_idx, catw_idx, eigen_idx, out_grad, n_grad, true);
 }
 
-int hp_pre_gradients_device(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int eigen_idx,
-                            double* d_grad, int n_grad) {
-    return run_pre(inst, ops, count, freq_idx, eigen_idx, d_grad, n_grad, true, true);
+int hp_pre_gradients_device(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx, int catw_idx,
+                            int eigen_idx, double* d_grad, int n_grad) {
+    return run_pre(inst, ops, count, freq_idx, catw_idx, eigen_idx, d_grad, n_grad, true, true);
 }
 
 // ------------------------------------------------------------------ whole-tree evaluation
@@ -1064,8 +1112,10 @@ int hp_set_tree(hp_instance* inst, const int32_t* children) {
     return HP_OK;
 }
 
-static int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out,
-                            bool rate_grad = false) {
+}  // extern "C"
+
+namespace hp {
+int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out, bool rate_grad) {
     const int N = I->d.n_tips;
     if (I->eig) {
         HP_HIP(I, timed(I, hp::kTraversal, [&] { return hp::launch_eig_evaluate(*I, d_t, want_grad, d_out); }));
@@ -1090,6 +1140,10 @@ static int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, doubl
     HP_HIP(I, HP_REDUCE(*I, 1 + a.n_grad + (rate_grad ? S * S : 0), d_out));
     return HP_OK;
 }
+}  // namespace hp
+
+extern "C" {
+using hp::enqueue_evaluate;
 
 static int check_eval_state(Instance* I) {
     if (!I->tree_set) return fail(I, HP_ERR_STATE, "hp_set_tree was not called");
@@ -1111,7 +1165,7 @@ int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_l
     rc = upload_async(I, I->ws + I->L.t_stage, t, (size_t)nb * 8);
     if (rc) return rc;
     double* d_out = I->at<double>(I->L.results);
-    rc = enqueue_evaluate(I, I->at<double>(I->L.t_stage), want_grad, d_out);
+    rc = enqueue_evaluate(I, I->at<double>(I->L.t_stage), want_grad, d_out, false);
     if (rc) return rc;
     const int n_out = want_grad ? 1 + nb : 1;
     HP_HIP(I, hipMemcpyAsync(I->host_out, d_out, (size_t)n_out * 8, hipMemcpyDeviceToHost, I->stream));
@@ -1135,7 +1189,7 @@ int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, doub
     int rc = check_eval_state(I);
     if (rc) return rc;
     DeviceGuard g(I->d.device);
-    return enqueue_evaluate(I, d_t, want_grad, d_out);
+    return enqueue_evaluate(I, d_t, want_grad, d_out, false);
 }
 
 // The matrix-core kernel stages the rate-gradient products in LDS; FP64 with 64 padded states

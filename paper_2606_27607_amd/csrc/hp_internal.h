@@ -41,6 +41,10 @@ struct Layout {
     // byte offsets into the workspace
     size_t tips, pweights, post, post_exp, pre, mats, tiptab, eig, Qc, freq_c, freq_d, cat_d,
         t_stage, idx_stage, ops_stage, tree_ops, partials, results, status, site, total;
+    // cat_d: FP64 category rates [kMaxCategories], then one row of category weights
+    // [kMaxCategories] per slot (n_eigen slots).  status: int32 words, [0] the kernels'
+    // status bits, [1] inputs rejected by hp_evaluate_scratch's preparation kernel, [2] the
+    // value the last status read took
     // matrix-core path only: P^T in the compute type, and 16-bit P, P^T and Q operands
     size_t matsT = 0, mats16 = 0, matsT16 = 0, Q16 = 0;
     size_t desc = 0;      // whole-tree descriptors: traversal with and without gradients, matrices
@@ -176,6 +180,11 @@ struct Instance {
     template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
+// Precisions whose matrix-core products take 16-bit operands (P, P^T and Q in 16-bit copies).
+constexpr bool mfma16(int prec) { return prec == HP_PREC_BF16 || prec == HP_PREC_F16 || prec == HP_PREC_BF16X3; }
+// ... of which these also keep a lo BF16 part of every matrix entry.
+constexpr bool bf16_split(int prec) { return prec == HP_PREC_BF16 || prec == HP_PREC_BF16X3; }
+
 // Host-side round-to-nearest-even conversions for the 16-bit copies of Q.
 inline uint16_t to_bf16_bits(double v) {
     float f = static_cast<float>(v);
@@ -213,6 +222,7 @@ struct WalkArgs {
     int n_pre = 0;
     int root_buf = -1;     // kRootBuf: post buffer index (>= n_tips)
     int freq_idx = 0;
+    int catw_idx = 0;      // category-weight slot
     int eigen_idx = 0;
     int n_grad = 0;        // gradient slots; reduction rows hold 1 + n_grad values
     double* site = nullptr;
@@ -238,7 +248,16 @@ void tree_shape_mfma(const Instance& I, int* tiles_per_group, int* blocks_per_cu
 // n_blocks: the traversal launch's workgroups (0: I.n_blocks)
 hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first = 0, bool accumulate = false,
                          int n_blocks = 0);
+// Host runtime pieces shared with the scratch-backed evaluation (api.cpp).
+int fail_global(int code, const std::string& msg);   // message read by hp_last_error(NULL)
+int check_desc(const hp_desc* d);                     // HP_OK or an error (message set)
+void choose_launch_shape(Instance* I);                // tile and workgroup counts of the launches
+// Matrices, traversal and reduction of one whole-tree evaluation on I's stream: d_t (2N-2
+// branch lengths) and d_out (1 + 2N-2 values, or 1) are device pointers.
+int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out, bool rate_grad);
 hipError_t launch_fill_i32(const Instance& I, int32_t* p, int32_t v, size_t n);
+// *taken = atomic exchange of *status with 0 (one thread, on I's stream)
+hipError_t launch_status_take(const Instance& I, int32_t* status, int32_t* taken);
 hipError_t launch_fill_u8(const Instance& I, uint8_t* p, uint8_t v, size_t n);
 hipError_t launch_fill_f64(const Instance& I, double* p, double v, size_t n);
 

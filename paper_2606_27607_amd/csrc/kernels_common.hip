@@ -131,7 +131,8 @@ void pmat_dispatch(const Instance& I, Args... args) {
     };
     switch (I.d.precision) {
         case HP_PREC_F64: by_states(TypeTag<double>{}, TypeTag<_Float16>{}); break;
-        case HP_PREC_BF16: by_states(TypeTag<float>{}, TypeTag<__bf16>{}); break;
+        case HP_PREC_BF16:
+        case HP_PREC_BF16X3: by_states(TypeTag<float>{}, TypeTag<__bf16>{}); break;
         default: by_states(TypeTag<float>{}, TypeTag<_Float16>{}); break;
     }
 }
@@ -182,6 +183,8 @@ __global__ void __launch_bounds__(256) reduce_batched(const BatchArgs b) {
     if (threadIdx.x == 0) b.out[q][j] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
+__global__ void status_take(int32_t* status, int32_t* taken) { *taken = atomicExch(status, 0); }
+
 template <typename T>
 __global__ void fill_kernel(T* __restrict__ p, T v, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -211,7 +214,7 @@ PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx) 
     d.matsT = L.matsT ? I.ws + L.matsT : nullptr;
     d.m16 = L.mats16 ? I.ws + L.mats16 : nullptr;
     d.mT16 = L.matsT16 ? I.ws + L.matsT16 : nullptr;
-    d.lo_off = I.d.precision == HP_PREC_BF16 ? (size_t)I.d.n_matrices * L.mat_stride : 0;
+    d.lo_off = bf16_split(I.d.precision) ? (size_t)I.d.n_matrices * L.mat_stride : 0;
     d.status = I.at<int32_t>(L.status);
     d.K = I.d.n_categories;
     d.S = I.d.n_states;
@@ -272,6 +275,10 @@ hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first,
 }
 
 hipError_t launch_fill_i32(const Instance& I, int32_t* p, int32_t v, size_t n) { return fill(I, p, v, n); }
+hipError_t launch_status_take(const Instance& I, int32_t* status, int32_t* taken) {
+    hipLaunchKernelGGL(status_take, dim3(1), dim3(1), 0, I.stream, status, taken);
+    return hipGetLastError();
+}
 hipError_t launch_fill_u8(const Instance& I, uint8_t* p, uint8_t v, size_t n) { return fill(I, p, v, n); }
 hipError_t launch_fill_f64(const Instance& I, double* p, double v, size_t n) { return fill(I, p, v, n); }
 

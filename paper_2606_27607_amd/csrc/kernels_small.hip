@@ -539,7 +539,7 @@ WalkDev<T> make_desc(const Instance& I, const WalkArgs& w) {
     a.Q = I.at<T>(L.Qc) + (size_t)w.eigen_idx * I.S_pad * I.S_pad;
     a.freq = I.at<T>(L.freq_c) + (size_t)w.freq_idx * I.S_pad;
     a.cat_r = I.at<double>(L.cat_d);
-    a.cat_w = I.at<double>(L.cat_d) + kMaxCategories;
+    a.cat_w = I.at<double>(L.cat_d) + (size_t)(1 + w.catw_idx) * kMaxCategories;
     a.post_ops = w.post_ops;
     a.pre_ops = w.pre_ops;
     a.site = w.site;

@@ -111,7 +111,15 @@ class Instance:
 
     # ------------------------------------------------------------------ data
     def set_tip_states(self, tip: int, states):
+        """Tip states 0..S-1, S = unknown: a host array (validated by the library), or a
+        CUDA uint8 tensor of n_patterns values, copied stream-ordered on torch's current
+        stream (codes above S are read as unknown; device values are not validated)."""
         if hasattr(states, "data_ptr"):
+            torch = self.torch
+            if not (getattr(states, "is_cuda", False) and states.dtype == torch.uint8 and states.is_contiguous()
+                    and states.numel() == self.n_patterns):
+                raise ValueError("device tip states must be a contiguous CUDA uint8 tensor of n_patterns values")
+            self._bind_stream()
             self._call("hp_set_tip_states", int(tip), ctypes.c_void_p(states.data_ptr()), 1)
             return
         a = np.ascontiguousarray(np.asarray(states, dtype=np.uint8))
@@ -132,8 +140,8 @@ class Instance:
     def set_category_rates(self, r):
         self._call("hp_set_category_rates", _ptr(_f64(r, self.desc.n_categories)))
 
-    def set_category_weights(self, w):
-        self._call("hp_set_category_weights", _ptr(_f64(w, self.desc.n_categories)))
+    def set_category_weights(self, w, idx: int = 0):
+        self._call("hp_set_category_weights", int(idx), _ptr(_f64(w, self.desc.n_categories)))
 
     def set_eigen(self, V, Vinv, lam, idx: int = 0):
         S = self.desc.n_states
@@ -159,28 +167,42 @@ class Instance:
         o = _i32(ops).reshape(-1, 6)
         self._call("hp_update_post", _ptr(o), int(o.shape[0]))
 
-    def root_lnl(self, root_buf: int, freq_idx: int = 0, site: bool = False):
+    def root_lnl(self, root_buf: int, freq_idx: int = 0, site: bool = False, catw_idx: int = 0):
         self._bind_stream()
         out = np.zeros(1)
         s = np.zeros(self.n_patterns) if site else None
-        self._call("hp_root_lnl", int(root_buf), int(freq_idx), _ptr(out),
+        self._call("hp_root_lnl", int(root_buf), int(freq_idx), int(catw_idx), _ptr(out),
                    _ptr(s) if site else ctypes.c_void_p())
         return (float(out[0]), s) if site else float(out[0])
+
+    def root_lnl_device(self, root_buf: int, out, site=None, freq_idx: int = 0, catw_idx: int = 0):
+        """Stream-ordered root integration into device memory: lnL into ``out`` (a CUDA
+        float64 tensor of at least one value, written at index 0) and, if given, the site
+        log-likelihoods into ``site`` (n_patterns values).  Returns ``out``."""
+        self._bind_stream()
+        for name, x, n in (("out", out, 1), ("site", site, self.n_patterns)):
+            if x is None:
+                continue
+            if not (x.is_cuda and x.dtype == self.torch.float64 and x.is_contiguous() and x.numel() >= n):
+                raise ValueError(f"{name} must be a contiguous CUDA float64 tensor of >= {n} values")
+        self._call("hp_root_lnl_device", int(root_buf), int(freq_idx), int(catw_idx),
+                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(site.data_ptr() if site is not None else None))
+        return out
 
     def update_pre(self, ops, freq_idx: int = 0):
         self._bind_stream()
         o = _i32(ops).reshape(-1, 9)
         self._call("hp_update_pre", _ptr(o), int(o.shape[0]), int(freq_idx))
 
-    def pre_gradients(self, ops, n_grad: int, freq_idx: int = 0, eigen_idx: int = 0):
+    def pre_gradients(self, ops, n_grad: int, freq_idx: int = 0, eigen_idx: int = 0, catw_idx: int = 0):
         self._bind_stream()
         o = _i32(ops).reshape(-1, 9)
         g = np.zeros(max(n_grad, 1))
-        self._call("hp_pre_gradients", _ptr(o), int(o.shape[0]), int(freq_idx), int(eigen_idx),
+        self._call("hp_pre_gradients", _ptr(o), int(o.shape[0]), int(freq_idx), int(catw_idx), int(eigen_idx),
                    _ptr(g), int(n_grad))
         return g[:n_grad]
 
-    def pre_gradients_device(self, ops, acc, freq_idx: int = 0, eigen_idx: int = 0):
+    def pre_gradients_device(self, ops, acc, freq_idx: int = 0, eigen_idx: int = 0, catw_idx: int = 0):
         """Stream-ordered form of :meth:`pre_gradients`: the list's gradients are added to
         ``acc`` (a contiguous CUDA float64 tensor of n_grad values; slots the list does not
         name gain +0).  Returns ``acc``."""
@@ -189,8 +211,8 @@ class Instance:
         if not (acc.is_cuda and acc.dtype == torch.float64 and acc.is_contiguous() and acc.numel() >= 1):
             raise ValueError("acc must be a contiguous CUDA float64 tensor")
         o = _i32(ops).reshape(-1, 9)
-        self._call("hp_pre_gradients_device", _ptr(o), int(o.shape[0]), int(freq_idx), int(eigen_idx),
-                   ctypes.c_void_p(acc.data_ptr()), int(acc.numel()))
+        self._call("hp_pre_gradients_device", _ptr(o), int(o.shape[0]), int(freq_idx), int(catw_idx),
+                   int(eigen_idx), ctypes.c_void_p(acc.data_ptr()), int(acc.numel()))
         return acc
 
     # ------------------------------------------------------------------ whole tree

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import announce, grad_err, make_instance, oracle_eval, rel
+from gpu_helpers import announce, grad_err, make_instance, oracle_eval, record, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +31,7 @@ def test_matches_oracle(precision, S, n, npat, K, seed):
     lnl_o, _, g_o = oracle_eval(wl)
     tl, tg = TOL[precision]
     print(f"S={S} N={n} P={npat} K={K} {precision}: lnL rel {rel(lnl, lnl_o):.2e} grad {grad_err(g, g_o):.2e}")
+    record(what="eig", lnl_rel=rel(lnl, lnl_o), grad=grad_err(g, g_o))
     assert rel(lnl, lnl_o) < tl and grad_err(g, g_o) < tg
     assert inst.evaluate(wl.t, want_grad=False) == lnl
 

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import announce, golden, grad_err, make_instance, rel
+from gpu_helpers import announce, golden, grad_err, make_instance, record, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -22,5 +22,6 @@ def test_geo200_full_size(precision, tl, tg):
     inst = make_instance(wl, precision, "every_node")
     lnl, g = inst.evaluate(wl.t)
     print(f"geo200 {precision}: lnL rel {rel(lnl, gold['lnl']):.2e} grad {grad_err(g, np.array(gold['grad'])):.2e}")
+    record(what="geo200", lnl_rel=rel(lnl, gold["lnl"]), grad=grad_err(g, np.array(gold["grad"])))
     assert rel(lnl, gold["lnl"]) < tl
     assert grad_err(g, np.array(gold["grad"])) < tg

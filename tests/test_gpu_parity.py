@@ -1,16 +1,17 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
 
-Tolerances: FP64 on the GPU agrees with the oracle to rounding (1e-12 relative on lnL,
-1e-11 of the largest gradient); FP32 meets the 1e-5 relative lnL bound and its gradient
-error is bounded at 1e-3 of the largest gradient (the derivation is in the design notes:
-per-pattern FP32 ratios carry ~1e-6 relative error and the branch gradient is a sum of
-terms of both signs).
+Tolerances (gpu_helpers.TOL): FP64 on the GPU agrees with the oracle to rounding (1e-12
+relative on lnL, 1e-11 of the largest gradient); FP32 meets the 1e-5 relative lnL bound and
+its gradient error is bounded at 1e-5 of the largest gradient and 1e-4 relative on every
+branch whose gradient is at least a tenth of the largest (per-pattern FP32 ratios carry
+~1e-7 relative error; the observed gradient error is ~2e-7 of max |g|).
 """
 import numpy as np
 import pytest
 
+import oracle
 import synth
-from gpu_helpers import (announce, golden, grad_err, make_instance, oracle_eval, post_ops, pre_ops,
+from gpu_helpers import (announce, check, golden, grad_err, make_instance, oracle_eval, post_ops, pre_ops,
                          rel)
 
 pytestmark = pytest.mark.gpu
@@ -30,12 +31,10 @@ def test_nuc8_fp64_full_config():
     inst = make_instance(wl, "f64", "none")
     lnl, g = inst.evaluate(wl.t)
     lnl_o, _, g_o = oracle_eval(wl)
-    assert rel(lnl, lnl_o) < 1e-12
-    assert grad_err(g, g_o) < 1e-11
+    check(lnl, lnl_o, g, g_o, "f64", what="nuc8")
     gold = golden("nuc8")
     if gold:
-        assert rel(lnl, gold["lnl"]) < 1e-12
-        assert grad_err(g, np.array(gold["grad"])) < 1e-11
+        check(lnl, gold["lnl"], g, np.array(gold["grad"]), "f64", what="nuc8 golden")
 
 
 @pytest.mark.parametrize("precision,scaling,period", [("f64", "every_node", 1), ("f64", "every_k", 3),
@@ -47,10 +46,7 @@ def test_evaluate_matches_oracle(precision, scaling, period, kind, n, npat, seed
     inst = make_instance(wl, precision, scaling, period)
     lnl, g = inst.evaluate(wl.t)
     lnl_o, _, g_o = oracle_eval(wl)
-    if precision == "f64":
-        assert rel(lnl, lnl_o) < 1e-12 and grad_err(g, g_o) < 1e-11
-    else:
-        assert rel(lnl, lnl_o) < 1e-5 and grad_err(g, g_o) < 1e-3
+    check(lnl, lnl_o, g, g_o, precision)
     lnl_only = inst.evaluate(wl.t, want_grad=False)
     assert lnl_only == lnl
 
@@ -62,8 +58,7 @@ def test_category_counts(K, precision):
     inst = make_instance(wl, precision, "every_node")
     lnl, g = inst.evaluate(wl.t)
     lnl_o, _, g_o = oracle_eval(wl)
-    tol = (1e-12, 1e-11) if precision == "f64" else (1e-5, 1e-3)
-    assert rel(lnl, lnl_o) < tol[0] and grad_err(g, g_o) < tol[1]
+    check(lnl, lnl_o, g, g_o, precision)
 
 
 @pytest.mark.parametrize("kind", ["bin", "three"])
@@ -72,7 +67,7 @@ def test_fewer_than_four_states(kind):
     inst = make_instance(wl, "f64", "every_node")
     lnl, g = inst.evaluate(wl.t)
     lnl_o, _, g_o = oracle_eval(wl)
-    assert rel(lnl, lnl_o) < 1e-12 and grad_err(g, g_o) < 1e-11
+    check(lnl, lnl_o, g, g_o, "f64")
 
 
 def test_two_taxon_jc69_closed_form_on_gpu():
@@ -99,10 +94,10 @@ def test_deep_caterpillar_needs_rescaling():
     lnl_o, _, g_o = oracle_eval(wl)
     inst = make_instance(wl, "f32", "every_k", 4)
     lnl, g = inst.evaluate(wl.t)
-    assert rel(lnl, lnl_o) < 1e-5 and grad_err(g, g_o) < 1e-3
+    check(lnl, lnl_o, g, g_o, "f32")
     inst64 = make_instance(wl, "f64", "every_k", 8)
     lnl64, g64 = inst64.evaluate(wl.t)
-    assert rel(lnl64, lnl_o) < 1e-12 and grad_err(g64, g_o) < 1e-10
+    check(lnl64, lnl_o, g64, g_o, "f64", scale=10)
 
 
 def test_single_pattern_and_zero_branch():
@@ -111,7 +106,7 @@ def test_single_pattern_and_zero_branch():
     inst = make_instance(wl, "f64", "every_node")
     lnl, g = inst.evaluate(wl.t)
     lnl_o, _, g_o = oracle_eval(wl)
-    assert rel(lnl, lnl_o) < 1e-12 and grad_err(g, g_o) < 1e-11
+    check(lnl, lnl_o, g, g_o, "f64")
 
 
 # --------------------------------------------------------------- operation-level API
@@ -130,7 +125,7 @@ def test_op_level_api(precision):
     assert rel(lnl, lnl_o) < tol
     assert np.allclose(site, site_o, rtol=tol, atol=0)
     g = inst.pre_gradients(pre_ops(wl.tree.children, N), nb)
-    assert grad_err(g, g_o) < (1e-11 if precision == "f64" else 1e-3)
+    check(lnl, lnl_o, g, g_o, precision, what="op-level")
     # pre partials alone, then the same list again with gradients: same answer
     inst.update_pre(pre_ops(wl.tree.children, N))
     g2 = inst.pre_gradients(pre_ops(wl.tree.children, N), nb)
@@ -211,8 +206,8 @@ def test_tile_shapes_match_oracle(force_small_ppl, ppl, precision, kind, n, npat
     assert inst.query(_lib.HP_Q_PATTERN_PAD) % 128 == 0
     lnl, g = inst.evaluate(wl.t)
     lnl_o, _, g_o = oracle_eval(wl)
-    tol = (1e-12, 1e-11) if precision == "f64" else (1e-5, 1e-3)
-    assert rel(lnl, lnl_o) < tol[0] and grad_err(g, g_o) < tol[1]
+    check(lnl, lnl_o, g, g_o, precision)
+    tol = (1e-12, 1e-11) if precision == "f64" else (1e-5, 1e-5)
     nb = 2 * n - 2
     inst.update_matrices(np.arange(nb), wl.t[:nb])
     inst.update_post(post_ops(wl.tree.children, n, rescale=1))
@@ -254,8 +249,8 @@ def test_tile_choice_and_batch_tile_check(force_small_ppl):
 
 # --------------------------------------------------------------- full-size configurations
 
-@pytest.mark.parametrize("precision,tol_l,tol_g", [("f32", 1e-5, 1e-3), ("f64", 1e-12, 1e-10)])
-def test_nuc128_full_size(precision, tol_l, tol_g):
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_nuc128_full_size(precision):
     """The benchmark workload at full size (128 taxa, 100,000 patterns, rescaling every 4
     levels) against the stored full-size oracle result."""
     gold = golden("nuc128")
@@ -265,8 +260,8 @@ def test_nuc128_full_size(precision, tol_l, tol_g):
     announce(f"nuc128 full size {precision}")
     inst = make_instance(wl, precision, "every_k", 4)
     lnl, g = inst.evaluate(wl.t)
-    assert rel(lnl, gold["lnl"]) < tol_l
-    assert grad_err(g, np.array(gold["grad"])) < tol_g
+    check(lnl, gold["lnl"], g, np.array(gold["grad"]), precision, what="nuc128 full size")
+    tol_l = 1e-12 if precision == "f64" else 1e-5
     # sampled site log-likelihoods from the operation-level root call
     inst.update_matrices(np.arange(254), wl.t[:254])
     inst.update_post(post_ops(wl.tree.children, 128, rescale=1))
@@ -373,3 +368,62 @@ def test_op_level_calls_across_stream_switches():
     many = run(make_instance(wl, "f32", "every_k", 4, tree=False), [streams[i % 2] for i in range(6)])
     for (l1, g1), (l2, g2) in zip(one, many):
         assert l1 == l2 and np.array_equal(g1, g2)
+
+    # switches between the stream-ordered calls themselves: the matrices are updated on stream
+    # A behind a kernel that keeps A busy for about a millisecond, and everything after it is
+    # issued on stream B without a host wait; the switch must order B after A's pending work
+    def run_split(inst):
+        out = []
+        a, b = streams
+        for rep in range(4):
+            t = wl.t[:nb] * (1.0 + 0.01 * rep)
+            lnl = torch.zeros(1, dtype=torch.float64, device="cuda")
+            acc = torch.zeros(nb, dtype=torch.float64, device="cuda")
+            with torch.cuda.stream(a):
+                torch.cuda._sleep(2_000_000)
+                inst.update_matrices(np.arange(nb), t)
+            with torch.cuda.stream(b):
+                inst.update_post(post)
+                inst.root_lnl_device(2 * N - 2, lnl)
+                inst.pre_gradients_device(pre, acc)
+            torch.cuda.synchronize()
+            out.append((lnl.item(), acc.cpu().numpy()))
+        return out
+
+    split = run_split(make_instance(wl, "f32", "every_k", 4, tree=False))
+    for (l1, g1), (l2, g2) in zip(one[:4], split):
+        assert l1 == l2 and np.array_equal(g1, g2)
+
+
+@pytest.mark.parametrize("kind,precision", [("gtr", "f64"), ("gtr", "f32"), ("gy94", "bf16"), ("aa", "bf16x3")])
+def test_op_level_device_calls_without_host_sync(kind, precision):
+    """One full evaluation through the operation-level calls with every result left in
+    device memory (hp_update_matrices, hp_update_post, hp_root_lnl_device with the site
+    values, hp_pre_gradients_device), synchronised once at the end, against the oracle; then
+    the same with a second category-weight slot holding other weights."""
+    import torch
+    wl = synth.make_workload(kind, 21, 700, seed=14, unknown_frac=0.05)
+    inst = make_instance(wl, precision, "every_node", tree=False, n_eigen=2)
+    N = wl.n_tips
+    nb = 2 * N - 2
+    post, pre = post_ops(wl.tree.children, N, rescale=1), pre_ops(wl.tree.children, N)
+    w2 = np.array([0.4, 0.3, 0.2, 0.1])
+    inst.set_category_weights(w2, idx=1)
+    for slot, cw in ((0, wl.cat_weights), (1, w2)):
+        announce(f"op-level device calls {kind} {precision} category-weight slot {slot}")
+        lnl = torch.zeros(1, dtype=torch.float64, device="cuda")
+        site = torch.zeros(wl.n_patterns, dtype=torch.float64, device="cuda")
+        acc = torch.zeros(nb, dtype=torch.float64, device="cuda")
+        inst.update_matrices(np.arange(nb), wl.t[:nb])
+        inst.update_post(post)
+        inst.root_lnl_device(2 * N - 2, lnl, site, catw_idx=slot)
+        inst.pre_gradients_device(pre, acc, catw_idx=slot)
+        torch.cuda.synchronize()
+        inst.status()
+        lnl_o, site_o, g_o = oracle.lnl_and_grad(wl.tree.children, N, wl.t, wl.Q, wl.pi, wl.rates, cw,
+                                                 wl.tips, wl.weights)
+        check(lnl.item(), lnl_o, acc.cpu().numpy(), g_o, precision, wl.n_states, what=f"device calls slot {slot}")
+        s = site.cpu().numpy()
+        assert np.max(np.abs(s - site_o)) < (1e-9 if precision == "f64" else 1e-3 if precision == "f32" else 0.05)
+        # the blocking calls give the same numbers
+        assert inst.root_lnl(2 * N - 2, catw_idx=slot) == lnl.item()

@@ -6,11 +6,14 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import announce, golden, grad_err, make_instance, rel
+from gpu_helpers import announce, check, golden, grad_err, make_instance, record, rel
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": (1e-12, 1e-10), "f32": (1e-5, 1e-3)}
+TOL = {"f64": (1e-12, 1e-10), "f32": (1e-5, 1e-5)}
+# G as a fraction of max |G|: tens of times the observed error (FP64 <= 6e-11, FP32 <= 3e-6,
+# 16-bit partials <= 5.5e-3: BF16 operands of the G products on both 16-bit paths)
+GTOL = {"f64": 1e-9, "f32": 5e-5, "bf16": 2e-2, "f16": 2e-2}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -44,8 +47,9 @@ def test_matches_oracle(monkeypatch, ppl, precision, kind, n, npat, K, seed):
                                     wl.tips, wl.weights)
     tl, tg = TOL[precision]
     assert G.shape == (wl.n_states, wl.n_states)
-    assert rel(lnl, lnl_o) < tl and grad_err(g, g_o) < tg
-    assert _g_err(G, G_o) < tg
+    check(lnl, lnl_o, g, g_o, precision, scale=10 if precision == "f64" else 1)
+    record(what="G", G=_g_err(G, G_o))
+    assert _g_err(G, G_o) < GTOL[precision]
     # the same lnL and branch gradients as the plain evaluation
     lnl2, g2 = inst.evaluate(wl.t)
     assert rel(lnl, lnl2) < tl * 1e-2 and grad_err(g, g2) < tg * 1e-2
@@ -83,7 +87,8 @@ def test_nuc128_full_size(precision):
     Go = np.array(gold["rate_grad"])
     tl, tg = TOL[precision]
     assert rel(lnl, gold["lnl"]) < tl
-    assert _g_err(G, Go) < tg
+    record(what="G", G=_g_err(G, Go))
+    assert _g_err(G, Go) < GTOL[precision]
     # along Q the first-order derivative is exact: sum_ij Q_ij G_ij = sum_c t_c g_c
     nb = 2 * wl.n_tips - 2
     assert rel(float(np.sum(wl.Q * G)), float(np.dot(wl.t[:nb], g))) < (1e-9 if precision == "f64" else 1e-4)
@@ -114,8 +119,9 @@ def test_matrix_core_path_matches_oracle(precision, kind, n, npat, K, seed):
     lnl_o, G_o = _oracle(wl)
     tl, tg = MTOL[precision]
     print(f"{kind} {precision} K={K}: G err {_g_err(G, G_o):.2e}")
+    record(what="G", lnl_rel=rel(lnl, lnl_o), G=_g_err(G, G_o))
     assert rel(lnl, lnl_o) < tl
-    assert _g_err(G, G_o) < tg
+    assert _g_err(G, G_o) < GTOL[precision]
     lnl2, g2 = inst.evaluate(wl.t)
     assert rel(lnl, lnl2) < 1e-12 and grad_err(g, g2) < 1e-9
     # along Q the first-order derivative is exact; the sum cancels (negative diagonal), so
@@ -137,4 +143,5 @@ def test_codon64_full_size(precision):
     Go = np.array(gold["rate_grad"])
     tl, tg = MTOL[precision]
     print(f"codon64 {precision}: G err {_g_err(G, Go):.2e}")
-    assert rel(lnl, gold["lnl"]) < tl and _g_err(G, Go) < tg
+    record(what="G", lnl_rel=rel(lnl, gold["lnl"]), G=_g_err(G, Go))
+    assert rel(lnl, gold["lnl"]) < tl and _g_err(G, Go) < GTOL[precision]

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import announce, grad_err, make_instance, oracle_eval, rel
+from gpu_helpers import announce, check, grad_err, make_instance, oracle_eval, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -105,7 +105,7 @@ def test_server_mix_equals_alone(budget_frac):
         lnl, g = results[[r[0] for r in reqs].index(c)]
         full_t = np.r_[t, 0.0]
         lnl_o, _, g_o = oracle_eval(wls[c], t=full_t)
-        assert rel(lnl, lnl_o) < 1e-4 and grad_err(g, g_o) < 5e-2
+        check(lnl, lnl_o, g, g_o, prec[wls[c].n_states], wls[c].n_states, what="serving mix")
 
 
 def test_chunked_session_matches_unchunked():
