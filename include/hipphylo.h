@@ -266,6 +266,20 @@ int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_l
  * output NaN and raises the status word read by hp_status (HP_ERR_VALUE). */
 int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, double* d_out);
 
+/* For callers that cannot allocate device memory or host staging at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the evaluation
+ * of hp_evaluate_device with its reduction scratch - the per-workgroup FP64 partial sums of
+ * lnL and of every gradient that a second kernel adds up in a fixed order - taken from a
+ * static device array of the library (16 MiB on each GPU the library runs on, held until
+ * the process ends) instead of the instance's workspace.  Same arguments, same kernels and
+ * bitwise the same results as hp_evaluate_device; stream-ordered, nothing is allocated or
+ * synchronised.  Evaluations needing more than 16 MiB of rows ((1 + 2N-2) x the launch's
+ * workgroups x 8 bytes with gradients, 8 bytes per workgroup without) are rejected with
+ * HP_ERR_WORKSPACE before anything is enqueued; more than 64 states is HP_ERR_UNSUPPORTED.
+ * Every call on one GPU shares that GPU's array: calls whose work overlaps on the device
+ * (other streams, other host threads) race and must be serialised by the caller. */
+int hp_evaluate_device_noalloc(hp_instance* inst, const double* d_t, int want_grad, double* d_out);
+
 /* Pre-order partials and all 2N-2 branch gradients of the tree of hp_set_tree from the
  * post-order partials and transition matrices left by the preceding
  * hp_evaluate_device(want_grad = 0) on this instance (the "store" form of a backward pass:

@@ -87,6 +87,7 @@ SIGNATURES = {
     "hp_plan_pre_buffers": [_I, _P, ctypes.POINTER(ctypes.c_int)],
     "hp_evaluate": [_P, _P, _I, _P, _P],
     "hp_evaluate_device": [_P, _P, _I, _P],
+    "hp_evaluate_device_noalloc": [_P, _P, _I, _P],
     "hp_gradients_device": [_P, _P],
     "hp_evaluate_rate_gradient": [_P, _P, _P, _P, _P],
     "hp_evaluate_rate_gradient_device": [_P, _P, _P],

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,11 +56,41 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 const char* const kEigWholeTreeOnly =
     "more than 64 states: only whole-tree evaluation (hp_set_tree, hp_evaluate[_device]) is supported";
 
+// ---- reduction rows of hp_evaluate_device_noalloc: one static device array per GPU
+// Every evaluation writes per-workgroup FP64 partial sums ([1 + 2N-2][workgroups]) that a
+// second kernel sums in a fixed order.  hp_evaluate_device keeps them in the caller's
+// workspace; the no-allocation variant keeps them here.  In host code `scratch` names a
+// host-side shadow, not device memory: the device address of each GPU's copy is looked up
+// once per device (hipGetSymbolAddress, with that device current) when the first instance
+// on it is created, and only that address is ever handed to kernels.
+constexpr size_t kNoallocBytes = size_t(16) << 20;
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoallocMaxDevices] = {};
+
+// The calling thread's current device must be `device`.
+hipError_t noalloc_init(int device) {
+    if (device < 0 || device >= kNoallocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* noalloc_ptr(int device) {
+    if (device < 0 || device >= kNoallocMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    return g_noalloc_ptr[device];
+}
+
 }  // namespace
 
 namespace hp {
-int fail_global(int code, const std::string& msg) { return fail(nullptr, code, msg); }
-
 int check_desc(const hp_desc* d) {
     if (!d) return fail(nullptr, HP_ERR_ARG, "descriptor is NULL");
     if (d->n_tips < 2) return fail(nullptr, HP_ERR_ARG, "n_tips must be >= 2");
@@ -485,6 +516,9 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
         return code;
     };
     if (!g.ok) return cleanup(fail(I, HP_ERR_DEVICE, "hipSetDevice failed"));
+    if (const hipError_t e = noalloc_init(desc->device); e != hipSuccess)
+        return cleanup(fail(I, HP_ERR_DEVICE, std::string("locating the static reduction rows: ") +
+                                                  hipGetErrorString(e)));
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, dev_workspace) != hipSuccess || attr.type != hipMemoryTypeDevice ||
         attr.device != desc->device) {
@@ -1115,7 +1149,8 @@ int hp_set_tree(hp_instance* inst, const int32_t* children) {
 }  // extern "C"
 
 namespace hp {
-int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out, bool rate_grad) {
+int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out, bool rate_grad,
+                     double* rows) {
     const int N = I->d.n_tips;
     if (I->eig) {
         HP_HIP(I, timed(I, hp::kTraversal, [&] { return hp::launch_eig_evaluate(*I, d_t, want_grad, d_out); }));
@@ -1135,9 +1170,10 @@ int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_ou
     a.pre_ops = a.post_ops + (size_t)(N - 1) * hp::kPostOpInts;
     a.n_pre = want_grad ? I->tree_n_pre : 0;
     a.n_grad = want_grad ? 2 * N - 2 : 0;
+    a.partials = rows;
     HP_HIP(I, HP_WALK(*I, a));
     const int S = I->d.n_states;
-    HP_HIP(I, HP_REDUCE(*I, 1 + a.n_grad + (rate_grad ? S * S : 0), d_out));
+    HP_HIP(I, HP_REDUCE(*I, 1 + a.n_grad + (rate_grad ? S * S : 0), d_out, 0, false, 0, rows));
     return HP_OK;
 }
 }  // namespace hp
@@ -1190,6 +1226,27 @@ int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, doub
     if (rc) return rc;
     DeviceGuard g(I->d.device);
     return enqueue_evaluate(I, d_t, want_grad, d_out, false);
+}
+
+int hp_evaluate_device_noalloc(hp_instance* inst, const double* d_t, int want_grad, double* d_out) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (!d_t || !d_out) return fail(I, HP_ERR_ARG, "NULL argument");
+    int rc = check_eval_state(I);
+    if (rc) return rc;
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, "more than 64 states: use hp_evaluate_device");
+    const size_t n_out = want_grad ? (size_t)(2 * I->d.n_tips - 1) : 1;
+    const size_t need = n_out * (size_t)I->n_blocks * sizeof(double);
+    if (need > kNoallocBytes)
+        return fail(I, HP_ERR_WORKSPACE,
+                    "the reduction rows of this evaluation (" + std::to_string(need) + " bytes) exceed the "
+                    "static array of hp_evaluate_device_noalloc (" + std::to_string(kNoallocBytes) + " bytes)");
+    double* rows = static_cast<double*>(noalloc_ptr(I->d.device));
+    if (!rows) return fail(I, HP_ERR_STATE, "the static reduction rows of this device were not located");
+    DeviceGuard g(I->d.device);
+    // every row slot the reduction reads is first written by this evaluation's traversal, so
+    // nothing left in the array by an earlier call is ever read
+    return enqueue_evaluate(I, d_t, want_grad, d_out, false, rows);
 }
 
 // The matrix-core kernel stages the rate-gradient products in LDS; FP64 with 64 padded states

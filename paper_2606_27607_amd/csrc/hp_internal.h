@@ -43,8 +43,7 @@ struct Layout {
         t_stage, idx_stage, ops_stage, tree_ops, partials, results, status, site, total;
     // cat_d: FP64 category rates [kMaxCategories], then one row of category weights
     // [kMaxCategories] per slot (n_eigen slots).  status: int32 words, [0] the kernels'
-    // status bits, [1] inputs rejected by hp_evaluate_scratch's preparation kernel, [2] the
-    // value the last status read took
+    // status bits, [2] the value the last status read took
     // matrix-core path only: P^T in the compute type, and 16-bit P, P^T and Q operands
     size_t matsT = 0, mats16 = 0, matsT16 = 0, Q16 = 0;
     size_t desc = 0;      // whole-tree descriptors: traversal with and without gradients, matrices
@@ -230,6 +229,9 @@ struct WalkArgs {
     // whole-tree evaluation (hp_set_tree's lists): for 4 < S the post buffers then hold
     // u_c = P_c post_c of each edge instead of post_c (see tree_mfma_body)
     bool tree = false;
+    // reduction rows the traversal writes ([1 + n_grad][n_blocks] FP64); null: the
+    // instance's own rows in its workspace
+    double* partials = nullptr;
 };
 hipError_t launch_walk(const Instance& I, const WalkArgs& a);
 // Size in bytes of the traversal descriptor for whole-tree evaluation, written to host_buf.
@@ -245,16 +247,15 @@ int small_blocks_per_cu(const Instance& I, int ppl);
 // workgroups per CU of the operation-level pre-order kernel (the heaviest one).
 void tree_shape_mfma(const Instance& I, int* tiles_per_group, int* blocks_per_cu, int* op_blocks_per_cu);
 // out[i] = sum over workgroups of reduction slot first + i, for i < n_out.
-// n_blocks: the traversal launch's workgroups (0: I.n_blocks)
+// n_blocks: the traversal launch's workgroups (0: I.n_blocks); rows: the reduction rows
+// (null: the instance's own)
 hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first = 0, bool accumulate = false,
-                         int n_blocks = 0);
-// Host runtime pieces shared with the scratch-backed evaluation (api.cpp).
-int fail_global(int code, const std::string& msg);   // message read by hp_last_error(NULL)
-int check_desc(const hp_desc* d);                     // HP_OK or an error (message set)
-void choose_launch_shape(Instance* I);                // tile and workgroup counts of the launches
+                         int n_blocks = 0, const double* rows = nullptr);
 // Matrices, traversal and reduction of one whole-tree evaluation on I's stream: d_t (2N-2
-// branch lengths) and d_out (1 + 2N-2 values, or 1) are device pointers.
-int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out, bool rate_grad);
+// branch lengths) and d_out (1 + 2N-2 values, or 1) are device pointers; rows: reduction
+// rows to use instead of the instance's own (null: its own).
+int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out, bool rate_grad,
+                     double* rows = nullptr);
 hipError_t launch_fill_i32(const Instance& I, int32_t* p, int32_t v, size_t n);
 // *taken = atomic exchange of *status with 0 (one thread, on I's stream)
 hipError_t launch_status_take(const Instance& I, int32_t* status, int32_t* taken);

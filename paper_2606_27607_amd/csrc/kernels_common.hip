@@ -267,9 +267,10 @@ hipError_t launch_walk(const Instance& I, const WalkArgs& w) {
     return launch_walk_mfma(I, w);
 }
 
-hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first, bool accumulate, int n_blocks) {
+hipError_t launch_reduce(const Instance& I, int n_out, double* d_out, int first, bool accumulate, int n_blocks,
+                         const double* rows) {
     if (n_out <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_rows, dim3(n_out), dim3(256), 0, I.stream, I.at<double>(I.L.partials),
+    hipLaunchKernelGGL(reduce_rows, dim3(n_out), dim3(256), 0, I.stream, rows ? rows : I.at<double>(I.L.partials),
                        n_blocks > 0 ? n_blocks : I.n_blocks, first, d_out, accumulate ? 1 : 0);
     return hipGetLastError();
 }

@@ -543,7 +543,7 @@ WalkDev<T> make_desc(const Instance& I, const WalkArgs& w) {
     a.post_ops = w.post_ops;
     a.pre_ops = w.pre_ops;
     a.site = w.site;
-    a.h.partials = I.at<double>(L.partials);
+    a.h.partials = w.partials ? w.partials : I.at<double>(L.partials);
     a.status = I.at<int32_t>(L.status);
     a.stride = L.post_stride;
     a.n_post = w.n_post;

@@ -246,6 +246,24 @@ class Instance:
                    ctypes.c_void_p(out.data_ptr()))
         return out
 
+    def evaluate_device_noalloc(self, t, want_grad: bool = True, out=None):
+        """:meth:`evaluate_device` with the reduction scratch in the library's static device
+        array (hp_evaluate_device_noalloc): nothing is allocated by the call when ``out`` is
+        given.  Calls whose work overlaps on one GPU share that array and race."""
+        self._bind_stream()
+        torch = self.torch
+        nb = 2 * self.n_tips - 2
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() >= nb):
+            raise ValueError("t must be a contiguous CUDA float64 tensor with 2N-2 values")
+        n_out = 1 + nb if want_grad else 1
+        if out is None:
+            out = torch.empty(n_out, dtype=torch.float64, device=self.device)
+        elif not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= n_out):
+            raise ValueError("out must be a contiguous CUDA float64 tensor with room for the results")
+        self._call("hp_evaluate_device_noalloc", ctypes.c_void_p(t.data_ptr()), int(bool(want_grad)),
+                   ctypes.c_void_p(out.data_ptr()))
+        return out
+
     def evaluate_rate_gradient(self, t):
         """(lnL, d lnL / d t_c for every branch, G): G[i, j] is the first-order approximation
         of d lnL / d Q_ij for the rate matrix of model slot 0 (whole-tree instances with
