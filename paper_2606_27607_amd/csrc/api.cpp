@@ -228,7 +228,11 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     l.tips = take((size_t)d.n_tips * P_pad);
     l.pweights = take((size_t)P_pad * 8);
     l.post = take(np * l.post_stride * elem);
-    l.post_exp = take(np * P_pad * 4);
+    // cumulative rescaling exponents: per pattern on the 4-state path; per pattern and
+    // category on the matrix-core path, whose whole-tree walk rescales each category on its
+    // own and also keeps the exponents of its pre-order partials
+    l.post_exp = take(np * (mfma ? K : 1) * P_pad * 4);
+    l.pre_exp = mfma ? take((size_t)n_pre(d) * K * P_pad * 4) : 0;
     l.pre = take((size_t)n_pre(d) * l.post_stride * elem);
     l.mats = take(nm * l.mat_stride * celem);
     if (mfma) l.matsT = take(nm * l.mat_stride * celem);

@@ -39,7 +39,7 @@ constexpr int kQSlots = 16;        // reduction slots of the rate-matrix gradien
 
 struct Layout {
     // byte offsets into the workspace
-    size_t tips, pweights, post, post_exp, pre, mats, tiptab, eig, Qc, freq_c, freq_d, cat_d,
+    size_t tips, pweights, post, post_exp, pre_exp, pre, mats, tiptab, eig, Qc, freq_c, freq_d, cat_d,
         t_stage, idx_stage, ops_stage, tree_ops, partials, results, status, site, total;
     // cat_d: FP64 category rates [kMaxCategories], then one row of category weights
     // [kMaxCategories] per slot (n_eigen slots).  status: int32 words, [0] the kernels'

@@ -122,8 +122,13 @@ def test_matrix_core_path_matches_oracle(precision, kind, n, npat, K, seed):
     record(what="G", lnl_rel=rel(lnl, lnl_o), G=_g_err(G, G_o))
     assert rel(lnl, lnl_o) < tl
     assert _g_err(G, G_o) < GTOL[precision]
+    # the plain evaluation runs the whole-tree walk that rescales each category on its own
+    # (the rate-gradient walk rescales per pattern): the same values up to rounding
     lnl2, g2 = inst.evaluate(wl.t)
-    assert rel(lnl, lnl2) < 1e-12 and grad_err(g, g2) < 1e-9
+    if precision == "f64":
+        assert rel(lnl, lnl2) < 1e-12 and grad_err(g, g2) < 1e-9
+    else:
+        assert rel(lnl, lnl2) < tl and grad_err(g, g2) < tg
     # along Q the first-order derivative is exact; the sum cancels (negative diagonal), so
     # its residual is measured against sum |Q_ij G_ij|
     nb = 2 * wl.n_tips - 2
