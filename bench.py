@@ -415,38 +415,57 @@ def measure_operation_level(wl, precision: str, steps: int) -> dict:
     whole = Instance(N, P, S, K, precision=precision, scaling=sc[0], scale_period=sc[1])
     whole.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights,
                children=wl.tree.children)
+    # the same calls with the Q . post cache (HP_FLAG_QPOST_CACHE, matrix-core path only)
+    cached = None
+    if 4 < S <= 64:
+        cached = Instance(N, P, S, K, precision=precision, scaling=sc[0], scale_period=sc[1],
+                          n_pre_partials=_lib.plan_pre_buffers(wl.tree.children), qpost_cache=True)
+        cached.load(wl.tips, wl.weights, wl.V, wl.Vinv, wl.lam, wl.pi, wl.rates, wl.cat_weights)
     t = wl.t[:nb]
     idx = np.arange(nb)
 
-    def op_eval():
-        op.update_matrices(idx, t)
-        op.update_post(post)
-        lnl = op.root_lnl(2 * N - 2)
-        return lnl, op.pre_gradients(pre, nb)
+    def op_eval(inst):
+        inst.update_matrices(idx, t)
+        inst.update_post(post)
+        lnl = inst.root_lnl(2 * N - 2)
+        return lnl, inst.pre_gradients(pre, nb)
 
     for _ in range(3):
-        lnl, g = op_eval()
+        lnl, g = op_eval(op)
         whole.evaluate(t)
-    t_op, t_whole = [], []
+        if cached is not None:
+            lnl_c, g_c = op_eval(cached)
+    t_op, t_whole, t_cached = [], [], []
     for _ in range(steps):
         t0 = time.perf_counter()
-        op_eval()
+        op_eval(op)
         t_op.append(time.perf_counter() - t0)
         t0 = time.perf_counter()
         whole.evaluate(t)
         t_whole.append(time.perf_counter() - t0)
+        if cached is not None:
+            t0 = time.perf_counter()
+            op_eval(cached)
+            t_cached.append(time.perf_counter() - t0)
     res = {"workload": wl.name, "precision": precision,
            "ms_per_eval_operation_level": 1000 * float(np.median(t_op)),
            "ms_per_eval_whole_tree": 1000 * float(np.median(t_whole))}
+    if cached is not None:
+        res["ms_per_eval_operation_level_qpost_cache"] = 1000 * float(np.median(t_cached))
     gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{wl.name}.json")
     if os.path.exists(gold_path):
         with open(gold_path) as f:
             gold = json.load(f)
         gg = np.array(gold["grad"])
-        res["error_vs_oracle"] = {"lnl_rel": abs(lnl - gold["lnl"]) / abs(gold["lnl"]),
-                                  "grad_maxabs_over_maxabs": float(np.max(np.abs(g - gg)) / np.max(np.abs(gg)))}
+        err = lambda l, gr: {"lnl_rel": abs(l - gold["lnl"]) / abs(gold["lnl"]),
+                             "grad_maxabs_over_maxabs": float(np.max(np.abs(gr - gg)) / np.max(np.abs(gg)))}
+        res["error_vs_oracle"] = err(lnl, g)
+        if cached is not None:
+            res["error_vs_oracle_qpost_cache"] = err(lnl_c, g_c)
     op.close()
     whole.close()
+    if cached is not None:
+        cached.close()
     return res
 
 

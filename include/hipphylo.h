@@ -101,7 +101,21 @@ typedef struct hp_desc {
                               reuses them as the pre-order walk frees them and needs only
                               hp_plan_pre_buffers() of them (about the tree's height), so
                               a whole-tree instance can size its workspace with that      */
+    int32_t flags;         /* HP_FLAG_* bits (0: none)                                   */
 } hp_desc;
+
+/* Cache Q . post during the post-order traversal (Discussion: the product of the rate matrix
+ * and the post-order partial at each node is cached in the post-order pass, so that the
+ * gradient's sandwich needs S partial values instead of the S x S rate matrix).  For
+ * 4 < n_states <= 64 (HP_ERR_UNSUPPORTED otherwise).  Every hp_update_post then also writes
+ * w_v = Q post_v (Q of eigen slot 0, which must be set first) beside each destination
+ * buffer, and hp_update_matrices also forms the tip columns (Q P_k(t))[:, s]; hp_pre_gradients
+ * [_device] with eigen_idx 0 take each numerator as (P_c^T v_c) . w_c for an internal child and
+ * v_c . (Q P_c)[:, s] for a tip, instead of forming Q P_c post_c.  The workspace grows by one
+ * more post-order buffer (in the compute type: FP64, else FP32) per buffer and one tip table per
+ * matrix slot.  Whole-tree calls do
+ * not use the cache. */
+#define HP_FLAG_QPOST_CACHE 1
 
 typedef struct hp_instance hp_instance;
 

@@ -52,7 +52,10 @@ HP_Q_TILE = 6
 class hp_desc(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "n_tips", "n_patterns", "n_states", "n_categories", "n_partials", "n_matrices", "n_eigen",
-        "precision", "scaling", "scale_period", "device", "n_pre_partials")]
+        "precision", "scaling", "scale_period", "device", "n_pre_partials", "flags")]
+
+
+HP_FLAG_QPOST_CACHE = 1
 
 
 POST_OP_FIELDS = ("dest", "child1", "mat1", "child2", "mat2", "rescale")

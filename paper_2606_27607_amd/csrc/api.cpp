@@ -102,6 +102,9 @@ int check_desc(const hp_desc* d) {
     if (d->n_partials < 1 || d->n_matrices < 1 || d->n_eigen < 1)
         return fail(nullptr, HP_ERR_ARG, "n_partials, n_matrices and n_eigen must be >= 1");
     if (d->n_pre_partials < 0) return fail(nullptr, HP_ERR_ARG, "n_pre_partials must be >= 0");
+    if (d->flags & ~HP_FLAG_QPOST_CACHE) return fail(nullptr, HP_ERR_ARG, "unknown flag bits");
+    if ((d->flags & HP_FLAG_QPOST_CACHE) && (d->n_states <= 4 || d->n_states > hp::kMaxStates))
+        return fail(nullptr, HP_ERR_UNSUPPORTED, "the Q . post cache is for 4 < n_states <= 64");
     if (d->precision < HP_PREC_F64 || d->precision > HP_PREC_BF16X3)
         return fail(nullptr, HP_ERR_ARG, "unknown precision");
     if (d->scaling < HP_SCALE_NONE || d->scaling > HP_SCALE_EVERY_K_LEVELS)
@@ -234,6 +237,11 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     l.post_exp = take(np * (mfma ? K : 1) * P_pad * 4);
     l.pre_exp = mfma ? take((size_t)n_pre(d) * K * P_pad * 4) : 0;
     l.pre = take((size_t)n_pre(d) * l.post_stride * elem);
+    if (d.flags & HP_FLAG_QPOST_CACHE) {
+        // w_v = Q post_v per post buffer, and the tip columns (Q P)[:, s] per matrix slot
+        l.qpost = take(np * l.post_stride * celem);
+        l.qptab = take(nm * l.tip_stride * celem);
+    }
     l.mats = take(nm * l.mat_stride * celem);
     if (mfma) l.matsT = take(nm * l.mat_stride * celem);
     if (lowp) {  // hi and lo 16-bit parts of P and P^T (lo only used for BF16)
@@ -781,11 +789,13 @@ int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count) {
         if (rc) return rc;
         if (o.rescale != 0 && o.rescale != 1) return fail(I, HP_ERR_ARG, "rescale must be 0 or 1");
     }
+    if ((I->d.flags & HP_FLAG_QPOST_CACHE) && !I->eigen_set[0])
+        return fail(I, HP_ERR_STATE, "the Q . post cache needs the eigensystem of slot 0");
     DeviceGuard g(I->d.device);
     int rc = upload_async(I, I->ws + I->L.ops_stage, ops, (size_t)count * sizeof(hp_post_op));
     if (rc) return rc;
     hp::WalkArgs a;
-    a.mode = hp::kPost;
+    a.mode = (I->d.flags & HP_FLAG_QPOST_CACHE) ? (hp::kPost | hp::kQCache) : hp::kPost;
     a.post_ops = I->at<int32_t>(I->L.ops_stage);
     a.n_post = count;
     HP_HIP(I, HP_WALK(*I, a));
@@ -902,6 +912,8 @@ static int run_pre(hp_instance* inst, const hp_pre_op* ops, int count, int freq_
     }
     hp::WalkArgs a;
     a.mode = grad ? (hp::kPre | hp::kGrad) : hp::kPre;
+    // gradients of model slot 0 read the Q . post cache that hp_update_post keeps
+    if (grad && eigen_idx == 0 && (I->d.flags & HP_FLAG_QPOST_CACHE)) a.mode |= hp::kQCache;
     a.pre_ops = I->at<int32_t>(I->L.ops_stage);
     a.n_pre = count;
     a.freq_idx = freq_idx;

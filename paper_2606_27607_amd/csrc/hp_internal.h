@@ -34,6 +34,8 @@ enum WalkMode : int {
     kPre = 8,         // walk the pre-order list
     kGrad = 16,       // accumulate branch gradients during the pre-order walk
     kQGrad = 32,      // with kGrad: also the first-order rate-matrix gradient (S <= 4)
+    kQCache = 64,     // operation-level matrix-core walk: post-order also writes Q post of
+                      // each destination; the gradient reads it (HP_FLAG_QPOST_CACHE)
 };
 constexpr int kQSlots = 16;        // reduction slots of the rate-matrix gradient (S_pad^2, S <= 4)
 
@@ -46,6 +48,7 @@ struct Layout {
     // status bits, [2] the value the last status read took
     // matrix-core path only: P^T in the compute type, and 16-bit P, P^T and Q operands
     size_t matsT = 0, mats16 = 0, matsT16 = 0, Q16 = 0;
+    size_t qpost = 0, qptab = 0;  // HP_FLAG_QPOST_CACHE: Q post per post buffer, (Q P) tip columns
     size_t desc = 0;      // whole-tree descriptors: traversal with and without gradients, matrices
     // eigensystem path (S > 64): per-branch vectors [branch][K][P][S_pad], e factors
     // [branch][K][S_pad], V / V^-1 / V^T / V^-T and lambda of slot 0, level lists, children
@@ -96,6 +99,7 @@ struct PmatDev {
     void* matsT;
     void* m16;
     void* mT16;
+    void* qptab;          // null, or the (Q P)[:, s] tip columns in the compute type
     size_t lo_off;
     int32_t* status;
     int K, S, S_pad;

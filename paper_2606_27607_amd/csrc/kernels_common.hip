@@ -19,6 +19,9 @@ namespace {
 // Matrix-core path extras (null when unused): matsT[m][k][y][x] = P[x][y] in T, and 16-bit
 // copies of P and P^T in H (negative rounding residues clamped to 0 before the cast); for
 // BF16 a lo part (value - hi) follows lo_off elements later.
+// With the Q . post cache (qptab not null): qptab[m][k][s][x] = (Q P)[x][s] (s < S), the
+// propagated one-hot tip under Q, from V diag(lam exp(lam r t)) Vinv; column S (the unknown
+// tip) is Q 1 = 0 exactly.
 // SMAX: the padded state count the LDS arrays are sized for (S <= SMAX), so that small
 // state spaces keep many workgroups per CU.
 template <typename T, typename H, int SMAX>
@@ -27,6 +30,7 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
     __shared__ double VL[SMAX * SMAX];             // V
     __shared__ double ex[SMAX];                    // exp(lam_j r t)
     __shared__ double rs[SMAX];                    // rs[j] = exp(lam_j r t) sum_y Vinv[j][y]
+    __shared__ double lm[SMAX];                    // lam_j (Q . post cache only)
     const int K = d.K, S = d.S, S_pad = d.S_pad;
     const int m = d.idx ? d.idx[i] : i;
     const bool bad = !(tt >= 0.0) || isinf(tt);
@@ -54,7 +58,10 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
             }
         }
     }
-    for (int j = threadIdx.x; j < S; j += blockDim.x) ex[j] = exp(lam[j] * rt);
+    for (int j = threadIdx.x; j < S; j += blockDim.x) {
+        ex[j] = exp(lam[j] * rt);
+        lm[j] = lam[j];
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < S * S; e += blockDim.x) W[e] = ex[e / S] * W[e];
     __syncthreads();
@@ -98,6 +105,17 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
             for (int j = 0; j < S; ++j) v += VL[x * S + j] * rs[j];
         if (bad) v = NAN;
         Tt[S * S_pad + x] = T(v);
+    }
+    if (d.qptab) {
+        T* Qt = static_cast<T*>(d.qptab) + (size_t)(m * K + k) * (S + 1) * S_pad;
+        for (int e = threadIdx.x; e < (S + 1) * S_pad; e += blockDim.x) {
+            const int s = e / S_pad, x = e % S_pad;
+            double v = 0.0;
+            if (s < S && x < S)
+                for (int j = 0; j < S; ++j) v += VL[x * S + j] * lm[j] * W[j * S + s];
+            if (bad) v = NAN;
+            Qt[e] = T(v);
+        }
     }
 }
 
@@ -214,6 +232,7 @@ PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx) 
     d.matsT = L.matsT ? I.ws + L.matsT : nullptr;
     d.m16 = L.mats16 ? I.ws + L.mats16 : nullptr;
     d.mT16 = L.matsT16 ? I.ws + L.matsT16 : nullptr;
+    d.qptab = L.qptab ? I.ws + L.qptab : nullptr;
     d.lo_off = bf16_split(I.d.precision) ? (size_t)I.d.n_matrices * L.mat_stride : 0;
     d.status = I.at<int32_t>(L.status);
     d.K = I.d.n_categories;

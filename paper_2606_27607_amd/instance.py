@@ -35,13 +35,16 @@ class Instance:
     "every_node", "every_k" (with ``scale_period`` levels).  Buffer counts default to what
     :meth:`set_tree` / :meth:`evaluate` need for one tree; ``n_pre_partials`` (0: as many
     as post-order buffers) may be cut to ``_lib.plan_pre_buffers(children)`` for a
-    whole-tree instance, about half the workspace.
+    whole-tree instance, about half the workspace.  ``qpost_cache`` (4 < n_states <= 64) keeps
+    Q . post beside every post-order buffer for the operation-level gradient calls
+    (HP_FLAG_QPOST_CACHE).
     """
 
     def __init__(self, n_tips: int, n_patterns: int, n_states: int, n_categories: int = 4, *,
                  precision: str = "f32", scaling: str = "every_k", scale_period: int = 4,
                  n_partials: int | None = None, n_matrices: int | None = None, n_eigen: int = 1,
-                 device: int = 0, workspace_ptr: int | None = None, n_pre_partials: int = 0):
+                 device: int = 0, workspace_ptr: int | None = None, n_pre_partials: int = 0,
+                 qpost_cache: bool = False):
         import torch
         self._lib = _lib.load()
         self.torch = torch
@@ -51,7 +54,8 @@ class Instance:
             n_partials=n_partials if n_partials is not None else max(1, n_tips - 1),
             n_matrices=n_matrices if n_matrices is not None else max(1, 2 * n_tips - 2),
             n_eigen=n_eigen, precision=_lib.PRECISIONS[precision], scaling=_lib.SCALINGS[scaling],
-            scale_period=scale_period, device=device, n_pre_partials=n_pre_partials)
+            scale_period=scale_period, device=device, n_pre_partials=n_pre_partials,
+            flags=_lib.HP_FLAG_QPOST_CACHE if qpost_cache else 0)
         self.precision = precision
         nbytes = ctypes.c_size_t()
         check(self._lib, self._lib.hp_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))

@@ -68,6 +68,26 @@ def test_workspace_sizing(lib):
     assert rcb == 0
 
 
+def test_qpost_cache_flag(lib):
+    """HP_FLAG_QPOST_CACHE adds exactly one Q . post buffer per post-order buffer and one
+    (Q P) tip table per matrix slot to a matrix-core instance (each region 256-byte aligned),
+    and is refused elsewhere; unknown flag bits are refused."""
+    N, P, S, K = 20, 3000, 61, 4
+    base = dict(n_tips=N, n_patterns=P, n_states=S, n_categories=K, n_partials=N - 1,
+                n_matrices=2 * N - 2, precision=2)
+    rc0, n0 = ws_bytes(lib, desc(**base))
+    rc1, n1 = ws_bytes(lib, desc(**base, flags=_lib.HP_FLAG_QPOST_CACHE))
+    assert rc0 == 0 and rc1 == 0
+    P_pad, S_pad = (P + 191) // 192 * 192, 64
+    al = lambda x: (x + 255) // 256 * 256
+    qpost = al((N - 1) * K * P_pad * S_pad * 4)            # FP32: the compute type
+    qptab = al((2 * N - 2) * K * (S + 1) * S_pad * 4)      # FP32 tip columns
+    assert n1 - n0 == qpost + qptab
+    assert ws_bytes(lib, desc(flags=_lib.HP_FLAG_QPOST_CACHE))[0] == _lib.HP_ERR_UNSUPPORTED   # 4 states
+    assert ws_bytes(lib, desc(n_states=80, precision=0, flags=1))[0] == _lib.HP_ERR_UNSUPPORTED
+    assert ws_bytes(lib, desc(**base, flags=2))[0] == _lib.HP_ERR_ARG
+
+
 @pytest.mark.parametrize("field,value,code", [
     ("n_tips", 1, _lib.HP_ERR_ARG), ("n_patterns", 0, _lib.HP_ERR_ARG),
     ("n_states", 255, _lib.HP_ERR_UNSUPPORTED), ("n_states", 1, _lib.HP_ERR_UNSUPPORTED),
