@@ -270,7 +270,11 @@ int hp_plan_pre_buffers(int n_tips, const int32_t* children, int* out_count);
 /* One full evaluation on the tree of hp_set_tree with model slot 0: transition matrices
  * for all 2N-2 branches from t (FP64, 2N-2 values, indexed by node), post-order partials,
  * root integration, and, if want_grad, pre-order partials and all 2N-2 branch gradients.
- * Host pointers; blocking.  grad may be NULL when want_grad == 0. */
+ * Host pointers; blocking.  grad may be NULL when want_grad == 0.  A small 4-state problem
+ * with gradients (at most 64 taxa and 64 workgroups of 64 patterns, its matrices fitting one
+ * workgroup's LDS) runs as one kernel launch that takes t by value and writes the results
+ * straight to pinned host memory, bitwise equal to the three-launch form; it then leaves no
+ * partials or matrices in the workspace. */
 int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_lnl,
                 double* out_grad);
 

@@ -1159,15 +1159,47 @@ int hp_set_tree(hp_instance* inst, const int32_t* children) {
     I->tree_set = true;
     I->tree_n_post = N - 1;
     I->tree_n_pre = N - 1;
+    I->tree_pre_bufs = need;
     return HP_OK;
 }
 
 }  // extern "C"
 
 namespace hp {
+// The one-launch evaluation (kFused) serves 4-state whole-tree evaluations with gradients on
+// instances whose tree, matrices and partials fit one workgroup's LDS and that launch at most
+// kFusedMaxBlocks workgroups of 64 patterns (the tile of its walk), where the three launches
+// and their memory round trips, not bandwidth, bound the time.  It leaves no partials or
+// matrices in the workspace, so an evaluation without gradients (whose post-order partials
+// hp_gradients_device may read next) always takes the three launches.
+bool fused_eligible(const Instance* I, int want_grad) {
+    if (!want_grad || I->eig || I->S_pad != 4 || I->L.tile != kWave) return false;
+    if (2 * I->d.n_tips - 2 > kFusedMaxBranches || I->n_blocks > kFusedMaxBlocks) return false;
+    return fused_small_lds_bytes(*I, I->tree_pre_bufs, false) <= kFusedMaxLds;
+}
+
+FusedLaunch fused_launch(Instance* I, int want_grad) {
+    FusedLaunch L;
+    L.want_grad = want_grad;
+    L.counter = I->at<int32_t>(I->L.status) + 4;
+    L.n_blocks = I->n_blocks;
+    L.n_pre_buf = I->tree_pre_bufs;
+    // the partials join the matrices in LDS where they fit (the smallest trees), otherwise they
+    // stay in the workspace
+    L.lds_partials = fused_small_lds_bytes(*I, I->tree_pre_bufs, true) <= kFusedMaxLds;
+    return L;
+}
+
 int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_out, bool rate_grad,
                      double* rows) {
     const int N = I->d.n_tips;
+    if (!rate_grad && !rows && fused_eligible(I, want_grad)) {
+        FusedLaunch L = fused_launch(I, want_grad);
+        L.t_dev = d_t;
+        L.out = d_out;
+        HP_HIP(I, timed(I, hp::kTraversal, [&] { return hp::launch_fused_small(*I, L); }));
+        return HP_OK;
+    }
     if (I->eig) {
         HP_HIP(I, timed(I, hp::kTraversal, [&] { return hp::launch_eig_evaluate(*I, d_t, want_grad, d_out); }));
         HP_HIP(I, HP_REDUCE(*I, want_grad ? 2 * N - 1 : 1, d_out));
@@ -1214,12 +1246,29 @@ int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_l
     for (int c = 0; c < nb; ++c)
         if (!(t[c] >= 0.0) || !std::isfinite(t[c])) return fail(I, HP_ERR_VALUE, "branch length < 0 or not finite");
     DeviceGuard g(I->d.device);
+    const int n_out = want_grad ? 1 + nb : 1;
+    if (hp::fused_eligible(I, want_grad)) {
+        // one launch: branch lengths by value, results and the taken status word written by
+        // the kernel straight into the pinned host buffers, one wait
+        hp::FusedLaunch L = hp::fused_launch(I, want_grad);
+        L.t_host = t;
+        L.out = I->host_out;
+        L.out_status = I->host_status;
+        HP_HIP(I, timed(I, hp::kTraversal, [&] { return hp::launch_fused_small(*I, L); }));
+        HP_HIP(I, hipStreamSynchronize(I->stream));
+        *out_lnl = I->host_out[0];
+        if (want_grad) std::copy(I->host_out + 1, I->host_out + n_out, out_grad);
+        if (*I->host_status & hp::kStatusNumeric) {
+            *out_lnl = -INFINITY;
+            return fail(I, HP_ERR_NUMERIC, "a site likelihood was zero or not finite");
+        }
+        return HP_OK;
+    }
     rc = upload_async(I, I->ws + I->L.t_stage, t, (size_t)nb * 8);
     if (rc) return rc;
     double* d_out = I->at<double>(I->L.results);
     rc = enqueue_evaluate(I, I->at<double>(I->L.t_stage), want_grad, d_out, false);
     if (rc) return rc;
-    const int n_out = want_grad ? 1 + nb : 1;
     HP_HIP(I, hipMemcpyAsync(I->host_out, d_out, (size_t)n_out * 8, hipMemcpyDeviceToHost, I->stream));
     HP_HIP(I, hipStreamSynchronize(I->stream));
     *out_lnl = I->host_out[0];

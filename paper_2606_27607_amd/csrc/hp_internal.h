@@ -36,6 +36,9 @@ enum WalkMode : int {
     kQGrad = 32,      // with kGrad: also the first-order rate-matrix gradient (S <= 4)
     kQCache = 64,     // operation-level matrix-core walk: post-order also writes Q post of
                       // each destination; the gradient reads it (HP_FLAG_QPOST_CACHE)
+    kFused = 128,     // 4-state whole-tree evaluation in one launch: matrices formed by each
+                      // workgroup in LDS, last-workgroup pattern sums
+    kFusedLds = 256,  // with kFused: the partial buffers in LDS too
 };
 constexpr int kQSlots = 16;        // reduction slots of the rate-matrix gradient (S_pad^2, S <= 4)
 
@@ -168,6 +171,7 @@ struct Instance {
     std::vector<char> eigen_set, freq_set;
     bool tree_set = false;
     int tree_n_post = 0, tree_n_pre = 0;
+    int tree_pre_bufs = 0;          // pre-order buffers the whole-tree lists use
     double* host_out = nullptr;     // pinned host buffer for results
     int32_t* host_status = nullptr; // pinned
     // pinned host staging of the per-call uploads (operation lists, matrix indices, branch
@@ -238,6 +242,23 @@ struct WalkArgs {
     double* partials = nullptr;
 };
 hipError_t launch_walk(const Instance& I, const WalkArgs& a);
+// One-launch whole-tree evaluation of a small 4-state problem (kFused; see kernels_small.hip).
+constexpr int kFusedMaxBranches = 126;   // 2N - 2 for up to 64 taxa, passed by value
+constexpr int kFusedMaxBlocks = 64;      // workgroups of 64 patterns
+constexpr size_t kFusedMaxLds = 120 * 1024;   // dynamic, beside up to 33 KB of static LDS
+struct FusedLaunch {
+    int want_grad = 1;
+    const double* t_host = nullptr;   // branch lengths by value (copied into the arguments) ...
+    const double* t_dev = nullptr;    // ... or read from device memory
+    double* out = nullptr;            // 1 + 2N-2 (or 1) results
+    int32_t* out_status = nullptr;    // null: the status word stays for hp_status
+    int32_t* counter = nullptr;
+    int n_blocks = 0, n_pre_buf = 0;
+    bool lds_partials = false;         // partial buffers in LDS too, where they fit
+};
+// LDS bytes of one workgroup: matrices and tip tables, and the partial buffers if `partials`.
+size_t fused_small_lds_bytes(const Instance& I, int n_pre_buf, bool partials);
+hipError_t launch_fused_small(const Instance& I, const FusedLaunch& L);
 // Size in bytes of the traversal descriptor for whole-tree evaluation, written to host_buf.
 size_t build_tree_desc(const Instance& I, int want_grad, void* host_buf);
 PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx);

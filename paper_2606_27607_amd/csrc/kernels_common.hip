@@ -2,6 +2,7 @@
 // deterministic pattern reductions, and small fill kernels (used instead of hipMemset so
 // that enqueued work stays capturable in a HIP graph).
 #include "hp_internal.h"
+#include "pmat4.h"
 
 namespace hp {
 
@@ -39,6 +40,14 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
     const double* V = d.eig;
     const double* Vi = d.eig + S * S;
     const double* lam = d.eig + 2 * S * S;
+    if constexpr (SMAX == 4) {
+        // four states: one thread forms the matrix and its tip table (pmat4, shared with the
+        // one-launch evaluation); there are no matrix-core copies for this state space
+        if (threadIdx.x == 0)
+            pmat4<T, const double*>(V, Vi, lam, rt, bad, S, static_cast<T*>(d.mats) + (size_t)(m * K + k) * 16,
+                     static_cast<T*>(d.tiptab) + (size_t)(m * K + k) * (S + 1) * 4);
+        return;
+    }
     // V and V^-1 are staged in LDS four elements per thread at a time, so their loads are in
     // flight together instead of one round trip per element (or per product step)
     for (int e0 = 0; e0 < S * S; e0 += 4 * (int)blockDim.x) {

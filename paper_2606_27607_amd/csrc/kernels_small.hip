@@ -19,6 +19,7 @@
 
 #include "hp_internal.h"
 #include "lanes.h"
+#include "pmat4.h"
 
 namespace hp {
 namespace {
@@ -58,17 +59,17 @@ template <typename T>
 __device__ __forceinline__ T dot(const V4<T>& a, const V4<T>& b) {
     return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
 }
-// u = P v with P row-major 4x4 (row = from-state).
-template <typename T>
-__device__ __forceinline__ V4<T> matvec(cptr<T> P, const V4<T>& v) {
+// u = P v with P row-major 4x4 (row = from-state); P: constant-space (scalar loads) or LDS.
+template <typename T, typename Ptr>
+__device__ __forceinline__ V4<T> matvec(Ptr P, const V4<T>& v) {
     return {P[0] * v.x + P[1] * v.y + P[2] * v.z + P[3] * v.w,
             P[4] * v.x + P[5] * v.y + P[6] * v.z + P[7] * v.w,
             P[8] * v.x + P[9] * v.y + P[10] * v.z + P[11] * v.w,
             P[12] * v.x + P[13] * v.y + P[14] * v.z + P[15] * v.w};
 }
 // u = P^T v.
-template <typename T>
-__device__ __forceinline__ V4<T> mattvec(cptr<T> P, const V4<T>& v) {
+template <typename T, typename Ptr>
+__device__ __forceinline__ V4<T> mattvec(Ptr P, const V4<T>& v) {
     return {P[0] * v.x + P[4] * v.y + P[8] * v.z + P[12] * v.w,
             P[1] * v.x + P[5] * v.y + P[9] * v.z + P[13] * v.w,
             P[2] * v.x + P[6] * v.y + P[10] * v.z + P[14] * v.w,
@@ -136,9 +137,24 @@ struct ChildIn {
 // longer-lived waves with more independent memory operations each: the host picks PPL so
 // that the whole grid is resident at once where it can (a second, nearly empty round of
 // workgroups costs almost a full latency-bound tree walk).
+// Dynamic LDS of the fused launch (kFused): the workgroup's transition matrices and tip
+// tables, then, where they fit, its partial buffers, [buffer][category][lane] (otherwise
+// post, pre and pexp are null and the partials stay in the workspace).
+template <typename T>
+struct FusedLds {
+    T* mats = nullptr;       // [n_mat][K][16]
+    T* tiptab = nullptr;     // [n_mat][K][S + 1][4]
+    T* post = nullptr;       // [n_post][K][kWave][4]
+    T* pre = nullptr;        // [n_pre][K][kWave][4]
+    int32_t* pexp = nullptr; // [n_post][kWave]
+};
+
 template <typename T, int KMAX, int PPL, int MODE>
-__device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int block) {
+__device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int block,
+                                                const FusedLds<T>& fl = FusedLds<T>{}) {
     constexpr int TW = kWave * PPL;
+    constexpr bool kF = (MODE & kFused) != 0;
+    static_assert(!kF || PPL == 1, "the fused launch walks one pattern per lane");
     __shared__ int sh_e[2][2][KMAX][TW];
     __shared__ T sh_v[2][3][KMAX][TW];
     __shared__ double sh_q[(MODE & kQGrad) ? KMAX : 1][kQSlots];
@@ -188,13 +204,30 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
     // taken from registers (forwarding) instead of a store-load round trip.  Both keep the
     // exact values memory would have returned, so results do not change.
     constexpr bool kPf = PPL == 1;
+    // partials in LDS (kFusedLds, fixed at compile time so that the accesses are LDS
+    // instructions) or in the workspace
+    constexpr bool lds_part = (MODE & kFusedLds) != 0;
     auto post_ptr = [&](int c, int j) {
-        return a.post + (size_t)(c - a.N) * a.stride + ((size_t)k * a.P_pad + p0 + j * kWave) * 4;
+        if constexpr (lds_part) return fl.post + ((size_t)(c - a.N) * K + k) * kWave * 4 + lane * 4;
+        else return a.post + (size_t)(c - a.N) * a.stride + ((size_t)k * a.P_pad + p0 + j * kWave) * 4;
     };
     auto pre_ptr = [&](int q, int j) {
-        return a.pre + (size_t)q * a.stride + ((size_t)k * a.P_pad + p0 + j * kWave) * 4;
+        if constexpr (lds_part) return fl.pre + ((size_t)q * K + k) * kWave * 4 + lane * 4;
+        else return a.pre + (size_t)q * a.stride + ((size_t)k * a.P_pad + p0 + j * kWave) * 4;
     };
-    auto exp_ptr = [&](int c, int j) { return a.pexp + (size_t)(c - a.N) * a.P_pad + p0 + j * kWave; };
+    auto exp_ptr = [&](int c, int j) {
+        if constexpr (lds_part) return fl.pexp + (size_t)(c - a.N) * kWave + lane;
+        else return a.pexp + (size_t)(c - a.N) * a.P_pad + p0 + j * kWave;
+    };
+    // transition matrix m of this wave's category, and its tip table
+    auto mat_at = [&](int m) {
+        if constexpr (kF) return static_cast<const T*>(fl.mats + (size_t)(m * K + k) * 16);
+        else return as_const(a.mats + (size_t)(m * K + k) * 16);
+    };
+    auto tip_col = [&](int m) {
+        if constexpr (kF) return static_cast<const T*>(fl.tiptab + (size_t)(m * K + k) * (a.S + 1) * 4);
+        else return a.tiptab + (size_t)(m * K + k) * (a.S + 1) * 4;
+    };
     // load what a child edge needs unless the child is `fwd` (produced by the operation before)
     auto fetch = [&](int c, int fwd, ChildIn<T, PPL>& ci) {
         if (c < a.N) {
@@ -212,7 +245,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
     auto resolve = [&](int c, int m, const ChildIn<T, PPL>& ci, int fwd, const V4<T> (&fx)[PPL],
                        const int (&fe)[PPL], V4<T> (&u)[PPL], int (&e)[PPL]) {
         if (c < a.N) {
-            const T* col = a.tiptab + (size_t)(m * K + k) * (a.S + 1) * 4;
+            const T* col = tip_col(m);
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 e[j] = 0;
@@ -221,7 +254,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             return;
         }
         const bool f = c == fwd;
-        const cptr<T> Pm = as_const(a.mats + (size_t)(m * K + k) * 16);
+        const auto Pm = mat_at(m);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             e[j] = f ? fe[j] : ci.e[j];
@@ -361,7 +394,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 eb[j] = INT_MIN;
             }
             if (q1 >= 0) {
-                const cptr<T> Pm = as_const(a.mats + (size_t)(m1 * K + k) * 16);
+                const auto Pm = mat_at(m1);
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
                     qa[j] = mattvec(Pm, va[j]);
@@ -369,7 +402,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 }
             }
             if (q2 >= 0) {
-                const cptr<T> Pm = as_const(a.mats + (size_t)(m2 * K + k) * 16);
+                const auto Pm = mat_at(m2);
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
                     qb[j] = mattvec(Pm, vb[j]);
@@ -525,6 +558,108 @@ walk_small_batched(const BatchArgs b) {
     walk_small_body<T, KMAX, PPL, MODE>(a, blockIdx.x - b.walk_off[i]);
 }
 
+// ---------------------------------------------------------------- one-launch evaluation
+// A whole-tree evaluation of a small problem (at most 64 taxa and a few thousand patterns)
+// is bound by the latency of its launches and memory round trips, not by bandwidth.  This
+// kernel does all of it in one launch:
+//   1. every workgroup forms the transition matrices and tip tables of all branches in its
+//      own LDS (the FP64 arithmetic and summation order of pmat_body, so the values are
+//      bitwise those of the matrix kernel);
+//   2. it walks the tree for its 64 patterns with walk_small_body, partials held in LDS;
+//   3. the last workgroup to finish (a device-scope counter) sums the reduction rows in
+//      the fixed order of reduce_rows and writes the results (to device memory, or straight
+//      to the caller's pinned host buffer), with the status word taken for the blocking
+//      call, and resets the counter for the next launch.
+// Results are bitwise those of the three-launch evaluation.
+template <typename T>
+struct FusedArgs {
+    WalkDev<T> a;
+    const double* eig;       // V, V^-1, lambda of model slot 0 (FP64)
+    const double* t_dev;     // branch lengths in device memory, or null: t below
+    double* out;             // 1 + n_grad results (device or pinned host memory)
+    int32_t* out_status;     // null, or where the taken status word goes (pinned host)
+    int32_t* counter;        // workgroups finished; zero between launches
+    int n_mat, n_post_buf, n_pre_buf;
+    double t[kFusedMaxBranches];
+};
+
+template <typename T, int KMAX, int MODE>
+__global__ void __launch_bounds__(KMAX * kWave) walk_small_fused(const FusedArgs<T> f) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+    const WalkDev<T>& a = f.a;
+    const int K = a.K, S = a.S;
+    FusedLds<T> fl;
+    T* base = reinterpret_cast<T*>(dyn);
+    fl.mats = base;
+    base += (size_t)f.n_mat * K * 16;
+    fl.tiptab = base;
+    base += (size_t)f.n_mat * K * (S + 1) * 4;
+    if constexpr ((MODE & kFusedLds) != 0) {
+        fl.post = base;
+        base += (size_t)f.n_post_buf * K * kWave * 4;
+        fl.pre = base;
+        base += (size_t)f.n_pre_buf * K * kWave * 4;
+        fl.pexp = reinterpret_cast<int32_t*>(base);
+    }
+
+    // 1. P_k(t_m) = V diag(exp(lam r_k t_m)) V^-1 and the tip table, one (m, k) per thread
+    //    (pmat4, as the matrix kernel forms them)
+    // the eigensystem is read-only here: uniform scalar loads
+    const cptr<double> V = as_const(f.eig);
+    const cptr<double> Vi = V + S * S;
+    const cptr<double> lam = V + 2 * S * S;
+    for (int q = threadIdx.x; q < f.n_mat * K; q += blockDim.x) {
+        const int m = q / K, k = q % K;
+        const double tt = f.t_dev ? f.t_dev[m] : f.t[m];
+        const bool bad = !(tt >= 0.0) || isinf(tt);
+        if (bad) atomicOr(a.status, kStatusValue);
+        pmat4<T, cptr<double>>(V, Vi, lam, a.cat_r[k] * tt, bad, S, fl.mats + (size_t)q * 16, fl.tiptab + (size_t)q * (S + 1) * 4);
+    }
+    __syncthreads();
+
+    // 2. the walk, for this workgroup's 64 patterns
+    walk_small_body<T, KMAX, 1, MODE | kFused>(a, blockIdx.x, fl);
+    static_assert(kFusedMaxBlocks <= kWave, "the last workgroup reads one column per lane");
+
+    // 3. the last workgroup to finish sums every reduction row
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(f.counter, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // reduce_rows' order: thread t of 256 sums columns t, t + 256, ... (here at most 64
+    // columns, so threads 64..255 hold 0), a shuffle tree over each wave, then the four waves
+    // in order; each wave of this workgroup takes every (blockDim / 64)-th slot, with the
+    // column loads of all its slots in flight together
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int nb = a.h.n_blocks;
+    const int stride = blockDim.x / kWave;
+    constexpr int kSlotsAtOnce = 8;
+    for (int s0 = wave; s0 < a.h.n_out; s0 += stride * kSlotsAtOnce) {
+        double v[kSlotsAtOnce];
+#pragma unroll
+        for (int u = 0; u < kSlotsAtOnce; ++u) {
+            const int slot = s0 + u * stride;
+            v[u] = (slot < a.h.n_out && lane < nb) ? a.h.partials[(size_t)slot * nb + lane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSlotsAtOnce; ++u) {
+            double s = 0.0 + v[u];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+            const int slot = s0 + u * stride;
+            if (lane == 0 && slot < a.h.n_out) f.out[slot] = ((s + 0.0) + 0.0) + 0.0;
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (f.out_status) *f.out_status = atomicExch(a.status, 0);
+        *f.counter = 0;
+    }
+    __threadfence_system();
+}
+
 template <typename T>
 WalkDev<T> make_desc(const Instance& I, const WalkArgs& w) {
     const Layout& L = I.L;
@@ -634,7 +769,70 @@ struct OccupancyFn {
 
 int ppl_of(const Instance& I) { return I.L.tile / kWave; }
 
+template <typename T>
+size_t fused_lds_bytes(const Instance& I, int n_pre_buf, bool partials) {
+    const size_t N = I.d.n_tips, K = I.d.n_categories, S = I.d.n_states, n_mat = 2 * N - 2;
+    const size_t mats = sizeof(T) * (n_mat * K * 16 + n_mat * K * (S + 1) * 4);
+    if (!partials) return mats;
+    return mats + sizeof(T) * (N - 1 + n_pre_buf) * K * kWave * 4 + 4 * (N - 1) * kWave;
+}
+
+template <typename T, int KMAX, int MODE>
+hipError_t launch_fused_t(const Instance& I, const FusedLaunch& L) {
+    FusedArgs<T> f{};
+    WalkArgs w;
+    w.mode = MODE;
+    w.tree = true;
+    w.post_ops = I.at<int32_t>(I.L.tree_ops);
+    w.n_post = I.tree_n_post;
+    w.pre_ops = w.post_ops + (size_t)(I.d.n_tips - 1) * kPostOpInts;
+    w.n_pre = (MODE & kPre) ? I.tree_n_pre : 0;
+    w.n_grad = (MODE & kGrad) ? 2 * I.d.n_tips - 2 : 0;
+    f.a = make_desc<T>(I, w);
+    f.a.h.n_blocks = L.n_blocks;
+    f.eig = I.at<double>(I.L.eig);
+    f.t_dev = L.t_dev;
+    f.out = L.out;
+    f.out_status = L.out_status;
+    f.counter = L.counter;
+    f.n_mat = 2 * I.d.n_tips - 2;
+    f.n_post_buf = I.d.n_tips - 1;
+    f.n_pre_buf = L.n_pre_buf;
+    if (L.t_host)
+        for (int i = 0; i < f.n_mat; ++i) f.t[i] = L.t_host[i];
+    const size_t lds = fused_lds_bytes<T>(I, L.n_pre_buf, L.lds_partials);
+    // the dynamic LDS limit is raised once per device for each instantiation
+    static bool raised[64] = {};
+    if (I.d.device >= 0 && I.d.device < 64 && !raised[I.d.device]) {
+        const void* fn = reinterpret_cast<const void*>(&walk_small_fused<T, KMAX, MODE>);
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedMaxLds);
+        if (e != hipSuccess) return e;
+        raised[I.d.device] = true;
+    }
+    hipLaunchKernelGGL((walk_small_fused<T, KMAX, MODE>), dim3(L.n_blocks), dim3(kWave * I.d.n_categories), lds,
+                       I.stream, f);
+    return hipGetLastError();
+}
+
+template <typename T, int KMAX>
+hipError_t launch_fused_k(const Instance& I, const FusedLaunch& L) {
+    constexpr int kAll = kPost | kRootFused | kPre | kGrad;
+    return L.lds_partials ? launch_fused_t<T, KMAX, kAll | kFusedLds>(I, L) : launch_fused_t<T, KMAX, kAll>(I, L);
+}
+
 }  // namespace
+
+size_t fused_small_lds_bytes(const Instance& I, int n_pre_buf, bool partials) {
+    return I.d.precision == HP_PREC_F64 ? fused_lds_bytes<double>(I, n_pre_buf, partials)
+                                        : fused_lds_bytes<float>(I, n_pre_buf, partials);
+}
+
+hipError_t launch_fused_small(const Instance& I, const FusedLaunch& L) {
+    const bool k4 = I.d.n_categories <= 4;
+    if (I.d.precision == HP_PREC_F64)
+        return k4 ? launch_fused_k<double, 4>(I, L) : launch_fused_k<double, 8>(I, L);
+    return k4 ? launch_fused_k<float, 4>(I, L) : launch_fused_k<float, 8>(I, L);
+}
 
 // Workgroups of the whole-tree kernel (with gradients) that one CU holds at once, for a
 // given number of patterns per lane; 0 if the runtime cannot tell.
