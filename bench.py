@@ -544,7 +544,7 @@ def serving_inputs(n_clients: int, jobs: int):
     return [got[c] for c in range(n_clients)]
 
 
-def serving_bench(inputs, loads=(0.5, 0.8, 1.0), seed: int = 20260055) -> dict:
+def serving_bench(inputs, loads=(0.5, 0.8, 1.0, 1.5), seed: int = 20260055) -> dict:
     """Many clients, continuous batching: isolated capacity, then Poisson arrivals at
     fractions of it; latency from submission to result, alone-vs-mix equality, and the
     oracle error on a stratified sample of clients."""
@@ -568,18 +568,24 @@ def serving_bench(inputs, loads=(0.5, 0.8, 1.0), seed: int = 20260055) -> dict:
     chunks = {c: srv.register(c, Dataset.from_workload(wl)) for c, (wl, _) in enumerate(inputs)}
     # isolated: one request at a time, each client's session loaded by an untimed first call
     t_start = time.perf_counter()
-    alone, service = {}, []
+    alone, service, service_small = {}, [], []
+    small = {c: all(s.tier == 0 for s in srv.sessions[c]) for c in range(n_clients)}
     for c, (wl, ts) in enumerate(inputs):
         srv.evaluate(c, ts[0])
         for r in range(len(ts)):
             s0 = time.perf_counter()
             alone[(c, r)] = srv.evaluate(c, ts[r])
             service.append(time.perf_counter() - s0)
+            if small[c]:
+                service_small.append(service[-1])
         if c % 16 == 15:
             print(f"[bench] serving: isolated pass, {c + 1} clients done", file=sys.stderr, flush=True)
     capacity = len(service) / sum(service)
     isolated = {"requests_per_s": capacity, "p50_ms": 1000 * float(np.percentile(service, 50)),
                 "p99_ms": 1000 * float(np.percentile(service, 99)),
+                "small_requests": len(service_small),
+                "small_p50_ms": 1000 * float(np.percentile(service_small or [0.0], 50)),
+                "small_p99_ms": 1000 * float(np.percentile(service_small or [0.0], 99)),
                 "seconds": time.perf_counter() - t_start, "evictions": srv.stats()["evictions"]}
     rng = np.random.default_rng(seed)
     mixes = []
@@ -607,6 +613,7 @@ def serving_bench(inputs, loads=(0.5, 0.8, 1.0), seed: int = 20260055) -> dict:
         mixes.append({"load": load, "offered_requests_per_s": load * capacity,
                       "requests_per_s": st["requests_per_s"], "p50_ms": st["p50_ms"],
                       "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "mean_batch": st["mean_batch"],
+                      "small_p50_ms": st["small_p50_ms"], "small_p99_ms": st["small_p99_ms"],
                       "batches": st["batches"], "max_concurrent_batches": st["max_concurrent_batches"],
                       "evictions": st["evictions"],
                       "algorithmic_GBs": sum(work_b[c] for c, _ in reqs) / span / 1e9,
@@ -638,7 +645,9 @@ def serving_bench(inputs, loads=(0.5, 0.8, 1.0), seed: int = 20260055) -> dict:
             "memory_budget_bytes": srv.memory_budget,
             "isolated": isolated, "mix": mixes, "mix_vs_alone_mismatches": mismatch,
             "error_vs_oracle_sample": err,
-            "arrivals": "Poisson, rate = load x isolated capacity, requests in random order"}
+            "small_session_seconds": srv.small_seconds,
+            "arrivals": "Poisson, rate = load x isolated capacity, requests in random order; "
+                        "small = requests whose sessions are all estimated under small_session_seconds"}
 
 
 def serving_cpu_baseline() -> dict:

@@ -142,20 +142,28 @@ typedef struct hp_pre_op {
 
 /* ---------------------------------------------------------------- lifecycle */
 
-/* Bytes of device workspace an instance with this descriptor needs (256-byte aligned). */
+/* Bytes of device workspace an instance with this descriptor needs (256-byte aligned): the
+ * partial-likelihood buffers, transition matrices and model of one data set, the library
+ * being an instance per data set or alignment block (Introduction; Benchmarks on NVIDIA and
+ * AMD GPUs, one instance per device on a block of patterns). */
 int hp_workspace_bytes(const hp_desc* desc, size_t* out_bytes);
 
-/* Create an instance on desc->device using the caller's workspace (device pointer,
+/* (Introduction: the library is created per data set and then driven call by call.)
+ * Create an instance on desc->device using the caller's workspace (device pointer,
  * 256-byte aligned, at least hp_workspace_bytes).  hip_stream may be NULL (the null
  * stream) or a hipStream_t.  Tip states start as "unknown", pattern weights as 1, the
  * category rates as 1 and the category weights as 1/K. */
 int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes,
               void* hip_stream, hp_instance** out);
+/* Release the instance (its host-side state; the caller frees the workspace). */
 int hp_destroy(hp_instance* inst);
-/* Work already issued on the previous stream is completed before the switch. */
+/* The stream all device work of the instance is ordered on (the library runs on a device
+ * beside its client; Introduction).  Work already issued on the previous stream is completed
+ * before the switch. */
 int hp_set_stream(hp_instance* inst, void* hip_stream);
 
-/* Copy the message of the last failed call on inst (or of hp_create if inst is NULL)
+/* (Library plumbing, not from the paper.)  Copy the message of the last failed call on inst
+ * (or of hp_create if inst is NULL)
  * into buf (always NUL-terminated when len > 0). */
 int hp_last_error(const hp_instance* inst, char* buf, size_t len);
 
@@ -173,27 +181,39 @@ int hp_query(const hp_instance* inst, int what, int64_t* out);
 
 /* ---------------------------------------------------------------- data */
 
-/* Tip states for one tip: states[n_patterns] with values 0..S-1, or S for unknown
+/* The observed sequence data whose likelihood is computed (Introduction; Scaling by number
+ * of taxa and site patterns: data are unique site patterns at the tips).
+ * Tip states for one tip: states[n_patterns] with values 0..S-1, or S for unknown
  * (all-ones partial).  on_device != 0: states is a device pointer (copied stream-ordered,
  * not validated); otherwise a host pointer (validated, copied before return). */
 int hp_set_tip_states(hp_instance* inst, int tip, const uint8_t* states, int on_device);
-/* Pattern weights c_p >= 0 (host, FP64, n_patterns values; non-integers allowed). */
+/* Pattern weights c_p >= 0 (host, FP64, n_patterns values; non-integers allowed): the count
+ * of each unique site pattern, lnL = sum_p c_p l_p (Scaling by number of taxa and site
+ * patterns). */
 int hp_set_pattern_weights(hp_instance* inst, const double* weights);
-/* Stationary frequencies of slot idx (host, FP64, S values, > 0, summing to 1 +- 1e-9). */
+/* Stationary frequencies of slot idx (host, FP64, S values, > 0, summing to 1 +- 1e-9): the
+ * distribution at the root of the CTMC substitution model (Algorithmic advances). */
 int hp_set_frequencies(hp_instance* inst, int idx, const double* pi);
-/* Rate-category rates r_k >= 0 (host FP64, K values), shared by every matrix and slot. */
+/* Rate-category rates r_k >= 0 (host FP64, K values), shared by every matrix and slot: rate
+ * heterogeneity across sites, each category a scaled copy of the CTMC (Discussion: the
+ * matrices of a substitution model are cached and reused across patterns). */
 int hp_set_category_rates(hp_instance* inst, const double* rates);
-/* Category weights w_k >= 0 of slot idx (host FP64, K values; n_eigen slots, each 1/K at
+/* (The mixture over rate categories, as for the rates above.)
+ * Category weights w_k >= 0 of slot idx (host FP64, K values; n_eigen slots, each 1/K at
  * creation).  The whole-tree calls use slot 0; the root and gradient calls name theirs. */
 int hp_set_category_weights(hp_instance* inst, int idx, const double* weights);
-/* Eigensystem of slot idx: row-major S x S V and Vinv with Q = V diag(lam) Vinv (host FP64).
+/* (Discussion: transition matrices come from a numerical eigendecomposition of the rate
+ * matrix.)  Eigensystem of slot idx: row-major S x S V and Vinv with Q = V diag(lam) Vinv
+ * (host FP64).
  * The library also forms Q itself in FP64, for the gradient. */
 int hp_set_eigen(hp_instance* inst, int idx, const double* V, const double* Vinv,
                  const double* lam);
 
 /* ---------------------------------------------------------------- transition matrices */
 
-/* For i < count: matrix slot mat_idx[i] <- P_k(t[i]) = V diag(exp(lam r_k t[i])) Vinv for
+/* (Discussion: the transition-probability matrices are formed from the eigendecomposition
+ * and cached for reuse across patterns.)
+ * For i < count: matrix slot mat_idx[i] <- P_k(t[i]) = V diag(exp(lam r_k t[i])) Vinv for
  * every category k, computed in FP64 and stored in the instance precision.  t: host FP64,
  * finite and >= 0 (HP_ERR_VALUE otherwise). */
 int hp_update_matrices(hp_instance* inst, int eigen_idx, const int32_t* mat_idx,
@@ -201,7 +221,8 @@ int hp_update_matrices(hp_instance* inst, int eigen_idx, const int32_t* mat_idx,
 
 /* ---------------------------------------------------------------- traversals */
 
-/* Post-order partial updates, in list order (children must be computed before use). */
+/* Post-order partial updates (Felsenstein's pruning, the post-order traversal; Introduction
+ * and Algorithmic advances), in list order (children must be computed before use). */
 int hp_update_post(hp_instance* inst, const hp_post_op* ops, int count);
 
 /* Root integration (the likelihood at the root of Felsenstein's pruning; Introduction) of
@@ -245,29 +266,48 @@ int hp_pre_gradients(hp_instance* inst, const hp_pre_op* ops, int count, int fre
 int hp_pre_gradients_device(hp_instance* inst, const hp_pre_op* ops, int count, int freq_idx,
                             int catw_idx, int eigen_idx, double* d_grad, int n_grad);
 
+/* A list mixing post-order and pre-order operations, taken in order in one launch, with the
+ * pre-order operations' branch gradients added into d_grad as by hp_pre_gradients_device: a
+ * backward pass that recomputes post-order partials right before the pre-order operations
+ * that read them, so that only some post-order partials need be kept between the passes
+ * (the pre-order traversal of Algorithmic advances; Discussion: caching strategies during
+ * the post- and pre-order traversals).  ops: count entries of 10 int32 each: a kind (0: a
+ * post-order operation, fields hp_post_op; 1: a pre-order operation, fields hp_pre_op) and
+ * its fields, unused trailing fields ignored; validated as those operations are, gradient
+ * slots distinct over the list.  n_states <= 4 (HP_ERR_UNSUPPORTED otherwise).
+ * Stream-ordered; the list is copied before return. */
+int hp_traverse_gradients_device(hp_instance* inst, const int32_t* ops, int count, int freq_idx,
+                                 int catw_idx, int eigen_idx, double* d_grad, int n_grad);
+
 /* ---------------------------------------------------------------- whole-tree evaluation */
 
-/* Fix the tree used by hp_evaluate*: children[2N-1][2] (row-major int32) in the standard
+/* (The post- and pre-order traversals of one tree; Algorithmic advances.)
+ * Fix the tree used by hp_evaluate*: children[2N-1][2] (row-major int32) in the standard
  * numbering (tips 0..N-1, internal N..2N-2, root 2N-2; tips have -1 children).  Internal
  * node v uses post buffer v and pre buffer v-N; branch c (the edge above node c) uses
  * matrix slot c and gradient slot c.  Builds and uploads the operation lists and the
  * rescaling plan once. */
 int hp_set_tree(hp_instance* inst, const int32_t* children);
 
-/* Host-only: the operation lists hp_set_tree builds for a children table, for inspection or
+/* (The traversal orders of Algorithmic advances, as operation lists.)
+ * Host-only: the operation lists hp_set_tree builds for a children table, for inspection or
  * for driving the operation-level calls.  out_post_ops receives N-1 hp_post_op (post-order,
  * children first, with the rescale flags of the given policy) and out_pre_ops N-1 hp_pre_op
  * (parents first).  Touches no device; the error message is read with hp_last_error(NULL). */
 int hp_plan_tree(int n_tips, const int32_t* children, int scaling, int scale_period,
                  int32_t* out_post_ops, int32_t* out_pre_ops);
 
-/* Host-only: the number of pre-order buffers hp_set_tree's operation lists use for this
+/* (Discussion: caching strategies during the post- and pre-order traversals.)
+ * Host-only: the number of pre-order buffers hp_set_tree's operation lists use for this
  * tree.  A pre-order partial lives from its parent's operation to its own, and the list
  * visits the tree depth-first, so buffers are handed out from a free list and the count is
  * bounded by the tree's height + 1 (the whole-tree lists need it in n_pre_partials). */
 int hp_plan_pre_buffers(int n_tips, const int32_t* children, int* out_count);
 
-/* One full evaluation on the tree of hp_set_tree with model slot 0: transition matrices
+/* The likelihood and its gradient with respect to every branch length in one post-order and
+ * one pre-order traversal (Algorithmic advances: linear in the number of tips; Scaling by
+ * number of taxa and site patterns: the lnL + gradient evaluation the HMC runs time).
+ * One full evaluation on the tree of hp_set_tree with model slot 0: transition matrices
  * for all 2N-2 branches from t (FP64, 2N-2 values, indexed by node), post-order partials,
  * root integration, and, if want_grad, pre-order partials and all 2N-2 branch gradients.
  * Host pointers; blocking.  grad may be NULL when want_grad == 0.  A small 4-state problem
@@ -278,7 +318,8 @@ int hp_plan_pre_buffers(int n_tips, const int32_t* children, int* out_count);
 int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_lnl,
                 double* out_grad);
 
-/* The same evaluation, fully stream-ordered: d_t (2N-2 FP64 branch lengths), d_out
+/* (As hp_evaluate; Algorithmic advances.)
+ * The same evaluation, fully stream-ordered: d_t (2N-2 FP64 branch lengths), d_out
  * (1 + 2N-2 FP64: lnL then gradients) are device pointers; nothing is synchronised.
  * Branch lengths are validated on the device: a negative or non-finite length makes the
  * output NaN and raises the status word read by hp_status (HP_ERR_VALUE). */
@@ -298,7 +339,8 @@ int hp_evaluate_device(hp_instance* inst, const double* d_t, int want_grad, doub
  * (other streams, other host threads) race and must be serialised by the caller. */
 int hp_evaluate_device_noalloc(hp_instance* inst, const double* d_t, int want_grad, double* d_out);
 
-/* Pre-order partials and all 2N-2 branch gradients of the tree of hp_set_tree from the
+/* (The pre-order traversal with the gradient sandwich; Algorithmic advances, Discussion.)
+ * Pre-order partials and all 2N-2 branch gradients of the tree of hp_set_tree from the
  * post-order partials and transition matrices left by the preceding
  * hp_evaluate_device(want_grad = 0) on this instance (the "store" form of a backward pass:
  * nothing from the forward pass is recomputed).  d_grad: device pointer, 2N-2 FP64 values
@@ -327,7 +369,8 @@ int hp_evaluate_rate_gradient_device(hp_instance* inst, const double* d_t, doubl
 
 /* ---------------------------------------------------------------- batched evaluation
  * Whole-tree evaluations of up to HP_MAX_BATCH instances in one launch per kernel (matrix
- * assembly, traversal, reduction), for serving many clients.  The instances must share
+ * assembly, traversal, reduction), for serving many clients (Benchmarks on NVIDIA and AMD
+ * GPUs: independent instances evaluate independent blocks of patterns at once).  The instances must share
  * device, precision, state padding, category count and tile (HP_Q_TILE), must each have had hp_set_tree and
  * model slot 0 set, and may each appear only once; their trees, pattern counts and models
  * may differ.  d_t[i] (2N_i-2 FP64) and d_out[i] (1 + 2N_i-2 FP64 with gradients, else 1)
@@ -339,7 +382,8 @@ int hp_evaluate_rate_gradient_device(hp_instance* inst, const double* d_t, doubl
 int hp_batch_evaluate_device(hp_instance* const* insts, const double* const* d_t,
                              double* const* d_out, int n, int want_grad, void* hip_stream);
 
-/* Synchronise the stream and return (then clear) the device-side status of work enqueued
+/* (Library plumbing, not from the paper.)
+ * Synchronise the stream and return (then clear) the device-side status of work enqueued
  * since the last call: HP_OK, HP_ERR_VALUE or HP_ERR_NUMERIC. */
 int hp_status(hp_instance* inst);
 

@@ -85,6 +85,7 @@ SIGNATURES = {
     "hp_update_pre": [_P, _P, _I, _I],
     "hp_pre_gradients": [_P, _P, _I, _I, _I, _I, _P, _I],
     "hp_pre_gradients_device": [_P, _P, _I, _I, _I, _I, _P, _I],
+    "hp_traverse_gradients_device": [_P, _P, _I, _I, _I, _I, _P, _I],
     "hp_set_tree": [_P, _P],
     "hp_plan_tree": [_I, _P, _I, _I, _P, _P],
     "hp_plan_pre_buffers": [_I, _P, ctypes.POINTER(ctypes.c_int)],

@@ -11,7 +11,9 @@ plus the segments on the current root-to-tip path, instead of N-1, at the cost o
 one more post-order pass and one launch per segment.
 
 Everything runs through the operation-level calls (hp_update_post, hp_root_lnl,
-hp_pre_gradients) of an instance created with the buffer counts the plan reports; the
+hp_pre_gradients; for four states the whole backward pass is one hp_traverse_gradients_device
+launch over the same operations as one list) of an instance created with the buffer counts
+the plan reports; the
 rescale flags are the library's own plan for the instance's scaling policy, so a
 recomputed partial is bitwise the one the forward pass produced.
 """
@@ -136,6 +138,13 @@ class CheckpointPlan:
         self.steps = steps
         self.n_post_buffers = pool.n
         self.n_pre_buffers = max(1, pre_pool.n)
+        # the same backward pass as one list for a single launch (hp_traverse_gradients_device):
+        # rows of (kind, fields), kind 0 for a recomputation, 1 for a pre-order operation
+        rows = []
+        for kind, ops in steps:
+            for r in ops:
+                rows.append(([0] + list(r) + [0] * 3) if kind == "post" else ([1] + list(r)))
+        self.mixed_ops = np.array(rows, dtype=np.int32).reshape(-1, 10)
 
     @property
     def n_segments(self) -> int:
@@ -215,6 +224,10 @@ class Checkpointed:
         torch = self.inst.torch
         nb = 2 * self.plan.n_tips - 2
         acc = torch.zeros(nb, dtype=torch.float64, device=self.inst.device)
+        if self.inst.desc.n_states <= 4:
+            # the 4-state walk takes the whole backward pass as one mixed list, one launch
+            self.inst.traverse_gradients_device(self.plan.mixed_ops, acc)
+            return acc.cpu().numpy()
         for kind, ops in self.plan.steps:
             if kind == "post":
                 self.inst.update_post(ops)

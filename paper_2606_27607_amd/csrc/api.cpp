@@ -949,6 +949,62 @@ int hp_pre_gradients_device(hp_instance* inst, const hp_pre_op* ops, int count, 
     return run_pre(inst, ops, count, freq_idx, catw_idx, eigen_idx, d_grad, n_grad, true, true);
 }
 
+int hp_traverse_gradients_device(hp_instance* inst, const int32_t* ops, int count, int freq_idx, int catw_idx,
+                                 int eigen_idx, double* d_grad, int n_grad) {
+    if (!inst) return HP_ERR_ARG;
+    auto* I = reinterpret_cast<Instance*>(inst);
+    if (I->eig || I->S_pad != 4)
+        return fail(I, HP_ERR_UNSUPPORTED, "mixed operation lists are for n_states <= 4");
+    if (count < 0 || (size_t)count * hp::kMixedOpInts > (size_t)max_ops(I->d) * hp::kPreOpInts)
+        return fail(I, HP_ERR_ARG, "bad operation count");
+    if (count > 0 && !ops) return fail(I, HP_ERR_ARG, "ops is NULL");
+    if (!d_grad) return fail(I, HP_ERR_ARG, "d_grad is NULL");
+    if (freq_idx < 0 || freq_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "frequency slot out of range");
+    if (!I->freq_set[freq_idx]) return fail(I, HP_ERR_STATE, "frequencies not set");
+    if (catw_idx < 0 || catw_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "category-weight slot out of range");
+    if (n_grad < 0 || n_grad > max_grad_slots(I->d)) return fail(I, HP_ERR_ARG, "bad n_grad");
+    if (eigen_idx < 0 || eigen_idx >= I->d.n_eigen) return fail(I, HP_ERR_INDEX, "eigen slot out of range");
+    if (!I->eigen_set[eigen_idx]) return fail(I, HP_ERR_STATE, "eigensystem not set");
+    // each entry is validated as the post- or pre-order operation it holds; gradient slots
+    // must be distinct over the whole list
+    std::vector<hp_pre_op> pre;
+    for (int i = 0; i < count; ++i) {
+        const int32_t* e = ops + (size_t)i * hp::kMixedOpInts;
+        if (e[0] == 0) {
+            hp_post_op o{e[1], e[2], e[3], e[4], e[5], e[6]};
+            int rc = check_post_buf(I, o.dest, "dest");
+            if (!rc) rc = check_child(I, o.child1, "child1");
+            if (!rc) rc = check_child(I, o.child2, "child2");
+            if (!rc) rc = check_mat(I, o.mat1);
+            if (!rc) rc = check_mat(I, o.mat2);
+            if (rc) return rc;
+            if (o.rescale != 0 && o.rescale != 1) return fail(I, HP_ERR_ARG, "rescale must be 0 or 1");
+        } else if (e[0] == 1) {
+            pre.push_back(hp_pre_op{e[1], e[2], e[3], e[4], e[5], e[6], e[7], e[8], e[9]});
+        } else {
+            return fail(I, HP_ERR_ARG, "operation kind must be 0 (post-order) or 1 (pre-order)");
+        }
+    }
+    int rc = check_pre_ops(I, pre.data(), (int)pre.size(), n_grad);
+    if (rc) return rc;
+    DeviceGuard g(I->d.device);
+    if (count > 0) {
+        rc = upload_async(I, I->ws + I->L.ops_stage, ops, (size_t)count * hp::kMixedOpInts * 4);
+        if (rc) return rc;
+    }
+    hp::WalkArgs a;
+    a.mode = hp::kMixed | hp::kGrad;
+    a.pre_ops = I->at<int32_t>(I->L.ops_stage);
+    a.n_pre = count;
+    a.freq_idx = freq_idx;
+    a.catw_idx = catw_idx;
+    a.eigen_idx = eigen_idx;
+    a.n_grad = n_grad;
+    HP_HIP(I, HP_WALK(*I, a));
+    HP_HIP(I, HP_REDUCE(*I, n_grad, d_grad, 1, true, op_blocks(I)));
+    return HP_OK;
+}
+
 // ------------------------------------------------------------------ whole-tree evaluation
 
 // Validate a children table and build the operation lists used for a whole-tree

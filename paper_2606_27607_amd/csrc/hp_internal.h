@@ -39,7 +39,9 @@ enum WalkMode : int {
     kFused = 128,     // 4-state whole-tree evaluation in one launch: matrices formed by each
                       // workgroup in LDS, last-workgroup pattern sums
     kFusedLds = 256,  // with kFused: the partial buffers in LDS too
+    kMixed = 512,     // 4-state walk of one list mixing post- and pre-order operations (with kGrad)
 };
+constexpr int kMixedOpInts = 10;   // kind (0 post, 1 pre), then the hp_post_op / hp_pre_op fields
 constexpr int kQSlots = 16;        // reduction slots of the rate-matrix gradient (S_pad^2, S <= 4)
 
 struct Layout {

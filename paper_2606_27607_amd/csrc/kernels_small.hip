@@ -262,6 +262,154 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
         }
     };
 
+    if constexpr ((MODE & kMixed) != 0) {
+        // One list of post-order and pre-order operations taken in order: a backward pass
+        // that recomputes post-order partials between the pre-order operations reading them
+        // (the checkpointed gradient).  Every operation loads its inputs and stores its
+        // results; the arithmetic of each is that of the loops below.
+        const T wk = T(as_const(a.cat_w)[k]);
+        const T wrk = T(as_const(a.cat_w)[k] * as_const(a.cat_r)[k]);
+        double cp[PPL];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) cp[j] = a.pw[p0 + j * kWave];
+        const int wave_b = K > 1 ? 1 : 0;
+        const V4<T> none[PPL] = {};
+        const int none_e[PPL] = {};
+        for (int i = 0; i < a.n_pre; ++i) {
+            cptr<int32_t> op = as_const(a.pre_ops + (size_t)i * kMixedOpInts);
+            if (op[0] == 0) {
+                const int dest = op[1], c1 = op[2], m1 = op[3], c2 = op[4], m2 = op[5], resc = op[6];
+                ChildIn<T, PPL> in1{}, in2{};
+                fetch(c1, -1, in1);
+                fetch(c2, -1, in2);
+                V4<T> u1[PPL], u2[PPL], x[PPL];
+                int e1[PPL], e2[PPL], E[PPL];
+                resolve(c1, m1, in1, -1, none, none_e, u1, e1);
+                resolve(c2, m2, in2, -1, none, none_e, u2, e2);
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    x[j] = mul(u1[j], u2[j]);
+                    E[j] = e1[j] + e2[j];
+                }
+                if (resc) {
+                    const int s = (sb++) & 1;
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) sh_e[s][0][k][lane + j * kWave] = scale_exp(max4(x[j]));
+                    __syncthreads();
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        int em = cat_max(sh_e[s][0], K, lane + j * kWave);
+                        em = (em == INT_MIN) ? 0 : em;
+                        x[j] = ldexp4(x[j], -em);
+                        E[j] += em;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    st4(post_ptr(dest, j), x[j]);
+                    if (k == 0) *exp_ptr(dest, j) = E[j];
+                }
+                continue;
+            }
+            const int pp = op[1];
+            const int c1 = op[2], m1 = op[3], q1 = op[4], g1 = op[5];
+            const int c2 = op[6], m2 = op[7], q2 = op[8], g2 = op[9];
+            ChildIn<T, PPL> in1{}, in2{};
+            fetch(c1, -1, in1);
+            fetch(c2, -1, in2);
+            V4<T> qn[PPL], ua[PPL], ub[PPL], va[PPL], vb[PPL], qa[PPL] = {}, qb[PPL] = {};
+            int e_unused[PPL], ea[PPL], eb[PPL];
+            const V4<T> fr = ld4(as_const(a.freq));
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) qn[j] = pp < 0 ? fr : ld4(pre_ptr(pp, j));
+            resolve(c1, m1, in1, -1, none, none_e, ua, e_unused);
+            resolve(c2, m2, in2, -1, none, none_e, ub, e_unused);
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                va[j] = mul(qn[j], ub[j]);
+                vb[j] = mul(qn[j], ua[j]);
+                ea[j] = INT_MIN;
+                eb[j] = INT_MIN;
+            }
+            if (q1 >= 0) {
+                const auto Pm = mat_at(m1);
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    qa[j] = mattvec(Pm, va[j]);
+                    if (a.rescale_pre) ea[j] = scale_exp(max4(qa[j]));
+                }
+            }
+            if (q2 >= 0) {
+                const auto Pm = mat_at(m2);
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    qb[j] = mattvec(Pm, vb[j]);
+                    if (a.rescale_pre) eb[j] = scale_exp(max4(qb[j]));
+                }
+            }
+            const bool grad = (MODE & kGrad) && (g1 >= 0 || g2 >= 0);
+            const bool resc = a.rescale_pre && (q1 >= 0 || q2 >= 0);
+            if (grad || resc) {
+                const int s = (sb++) & 1;
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    const int l = lane + j * kWave;
+                    if (resc) {
+                        sh_e[s][0][k][l] = ea[j];
+                        sh_e[s][1][k][l] = eb[j];
+                    }
+                    if (grad) {
+                        const cptr<T> Qp = as_const(a.Q);
+                        sh_v[s][0][k][l] = wk * dot(va[j], ua[j]);
+                        sh_v[s][1][k][l] = g1 >= 0 ? wrk * dot(va[j], matvec(Qp, ua[j])) : T(0);
+                        sh_v[s][2][k][l] = g2 >= 0 ? wrk * dot(vb[j], matvec(Qp, ub[j])) : T(0);
+                    }
+                }
+                __syncthreads();
+                if (resc) {
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        const int l = lane + j * kWave;
+                        ea[j] = cat_max(sh_e[s][0], K, l);
+                        eb[j] = cat_max(sh_e[s][1], K, l);
+                    }
+                }
+                if (grad) {
+                    for (int side = 0; side < 2; ++side) {
+                        const int g = side ? g2 : g1;
+                        if (g < 0 || k != (side ? wave_b : 0)) continue;
+                        double tot = 0.0;
+#pragma unroll
+                        for (int j = 0; j < PPL; ++j) {
+                            const int l = lane + j * kWave;
+                            double r;
+                            if constexpr (sizeof(T) == 4) {
+                                T den = 0, num = 0;
+#pragma unroll
+                                for (int kk = 0; kk < KMAX; ++kk) {
+                                    const T d = sh_v[s][0][kk][l], n = sh_v[s][1 + side][kk][l];
+                                    den += kk < K ? d : T(0);
+                                    num += kk < K ? n : T(0);
+                                }
+                                r = double(num * __builtin_amdgcn_rcpf(den));
+                            } else {
+                                r = cat_sum(sh_v[s][1 + side], K, l) / cat_sum(sh_v[s][0], K, l);
+                            }
+                            tot += cp[j] == 0.0 ? 0.0 : cp[j] * r;
+                        }
+                        tot = wave_sum(tot);
+                        if (lane == 0) a.h.partials[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                if (q1 >= 0) st4(pre_ptr(q1, j), ldexp4(qa[j], ea[j] == INT_MIN ? 0 : -ea[j]));
+                if (q2 >= 0) st4(pre_ptr(q2, j), ldexp4(qb[j], eb[j] == INT_MIN ? 0 : -eb[j]));
+            }
+        }
+    }
+
     if (MODE & kPost) {
         ChildIn<T, PPL> in1{}, in2{}, nx1{}, nx2{};
         int prev = -1;
@@ -712,6 +860,7 @@ hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
         case kPost | kRootFused | kPre | kGrad | kQGrad:
             HP_LAUNCH(kPost | kRootFused | kPre | kGrad | kQGrad);
             break;
+        case kMixed | kGrad: HP_LAUNCH(kMixed | kGrad); break;
         default: return hipErrorInvalidValue;
     }
 #undef HP_LAUNCH

@@ -219,6 +219,19 @@ class Instance:
                    int(eigen_idx), ctypes.c_void_p(acc.data_ptr()), int(acc.numel()))
         return acc
 
+    def traverse_gradients_device(self, ops, acc, freq_idx: int = 0, eigen_idx: int = 0, catw_idx: int = 0):
+        """One launch over a list mixing post-order (kind 0) and pre-order (kind 1)
+        operations, rows of 10 int32 (kind, then the operation's fields), gradients added to
+        ``acc`` as by :meth:`pre_gradients_device` (hp_traverse_gradients_device, n_states <= 4)."""
+        self._bind_stream()
+        torch = self.torch
+        if not (acc.is_cuda and acc.dtype == torch.float64 and acc.is_contiguous() and acc.numel() >= 1):
+            raise ValueError("acc must be a contiguous CUDA float64 tensor")
+        o = _i32(ops).reshape(-1, 10)
+        self._call("hp_traverse_gradients_device", _ptr(o), int(o.shape[0]), int(freq_idx), int(catw_idx),
+                   int(eigen_idx), ctypes.c_void_p(acc.data_ptr()), int(acc.numel()))
+        return acc
+
     # ------------------------------------------------------------------ whole tree
     def set_tree(self, children):
         c = _i32(children).reshape(-1, 2)

@@ -9,12 +9,21 @@ branch-length vectors; every request returns lnL and all 2N-2 branch gradients.
   whose session cannot be admitted waits.
 * A data set larger than the per-session cap is split into pattern chunks (patterns are
   conditionally independent given the tree and model); each chunk is its own sub-session
-  and the request's result is the sum over chunks, taken in chunk order.
+  and the request's result is the sum over chunks, taken in chunk order.  So is a data set
+  whose evaluation is estimated to take longer than `max_chunk_seconds` (chunks of at least
+  `min_chunk_patterns`): a long evaluation then reaches the device as several shorter
+  launches, between which other clients' work gets the compute units it would otherwise
+  wait for behind one long kernel.
 * A scheduler thread forms batches continuously: requests that arrive while earlier batches
   run are admitted as soon as memory and their session are free, and up to HP_MAX_BATCH
   sessions of one class (precision, state padding, categories) are evaluated by a single
   launch per kernel (hp_batch_evaluate_device) on that class's stream; several batches per
   class may be in flight and different classes overlap on the device.
+* Batching is size-aware.  A batch finishes with its slowest member, so each session's
+  evaluation time is estimated from its algorithmic bytes and flops, and sessions below
+  `small_seconds` form their own tier: small requests are batched with small requests, on
+  streams and in-flight slots of their own, and never wait behind a large evaluation of their
+  class.  Large sessions are batched only with sessions of similar cost.
 * Latency is measured from submission to result (p50 / p99), beside throughput.
 * A malformed request (wrong length, negative or non-finite branch length) fails with
   HP_ERR_VALUE on its own future; an error reported by the device for one session fails
@@ -80,6 +89,23 @@ class Dataset:
 
 def scaling_for(n_states, precision):
     return _lib.default_scaling(n_states, precision)
+
+
+ELEM_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "bf16x3": 4}
+
+
+def work_seconds(data: Dataset, precision: str, hbm_bytes_per_s: float = 5e12,
+                 flops_per_s: float = 100e12, fixed_s: float = 30e-6) -> float:
+    """Estimated device time of one evaluation with gradients: the algorithmic bytes of the
+    per-operation accounting (5 (N-2) partial-sized transfers) over a sustained bandwidth,
+    or the matrix products (4 per internal node, 2 S^2 flops per pattern and category) over a
+    sustained throughput, whichever is longer, plus a fixed launch cost.  Used only to order
+    and group work, never for results."""
+    N, P, S, K = data.n_tips, data.n_patterns, data.n_states, len(data.rates)
+    S_pad = 4 if S <= 4 else (32 if S <= 32 else 64)
+    nbytes = 5.0 * max(N - 2, 1) * P * K * S_pad * ELEM_BYTES.get(precision, 4) + 2.0 * N * P
+    flops = 0.0 if S <= 4 else 4.0 * max(N - 2, 1) * P * K * 2.0 * S * S
+    return max(nbytes / hbm_bytes_per_s, flops / flops_per_s) + fixed_s
 
 
 class DeviceMemory:
@@ -155,9 +181,15 @@ class Arena:
 
 
 class HipExecutor:
-    """Device side of the server: instances, batched launches on per-class streams."""
+    """Device side of the server: instances, batched launches on a few streams per size tier.
 
-    STREAMS_PER_CLASS = 4
+    The runtime maps streams onto a handful of hardware queues (four by default), and work on
+    one queue runs in order: a small batch placed behind a long evaluation on the same queue
+    waits for all of it.  So there are few streams, created together at start-up: two for
+    small batches and one for large ones, shared by every class, which keeps small work on
+    queues of its own."""
+
+    STREAMS = {0: 2, 1: 1}          # size tier -> streams
 
     def __init__(self, device: int = 0):
         import torch
@@ -165,7 +197,8 @@ class HipExecutor:
         self.lib = _lib.load()
         self.device_index = device
         self.device = torch.device("cuda", device)
-        self.streams = {}
+        self.streams = {tier: [torch.cuda.Stream(device=self.device) for _ in range(n)]
+                        for tier, n in self.STREAMS.items()}
         self.turn = collections.Counter()
         self.memory = DeviceMemory(device)
         self.arena = None
@@ -242,14 +275,11 @@ class HipExecutor:
     def launch(self, key, items):
         """items: [(session, t)].  Enqueue one batched evaluation; return a completion token."""
         torch = self.torch
-        # a few streams per class, in turn, so that a long batch does not hold up the next
-        # short one of the same class
-        pool = self.streams.get(key)
-        if pool is None:
-            pool = self.streams[key] = [torch.cuda.Stream(device=self.device)
-                                        for _ in range(self.STREAMS_PER_CLASS)]
-        stream = pool[self.turn[key] % len(pool)]
-        self.turn[key] += 1
+        # the streams of the batch's size tier (key: (class, tier)), in turn
+        tier = key[1] if isinstance(key, tuple) and len(key) == 2 and key[1] in self.streams else 1
+        pool = self.streams[tier]
+        stream = pool[self.turn[tier] % len(pool)]
+        self.turn[tier] += 1
         with torch.cuda.stream(stream):
             for s, t in items:
                 st = s.state
@@ -269,15 +299,23 @@ class HipExecutor:
         return (ev, items)
 
     def poll(self, token):
-        """None while running; then [(ok, result or exception)] per item."""
+        """None while running; then [(ok, result or exception)] per item.  Branch lengths
+        were validated on submission, so the only device-side error left is a zero or
+        non-finite site likelihood, which makes lnL -inf or NaN: the instance's status word
+        (read and cleared with a wait on its stream) is consulted only for such a result,
+        and a completed batch never waits on other work."""
         ev, items = token
         if not ev.query():
             return None
         res = []
         for s, _ in items:
+            out = s.state["out_host"].numpy().copy()
+            if np.all(np.isfinite(out)):
+                res.append((True, out))
+                continue
             try:
                 s.state["inst"].status()
-                res.append((True, s.state["out_host"].numpy().copy()))
+                res.append((False, _lib.HPError(_lib.HP_ERR_NUMERIC, "a site likelihood was zero or not finite")))
             except Exception as e:  # noqa: BLE001 - reported on that request only
                 res.append((False, e))
         return res
@@ -286,12 +324,14 @@ class HipExecutor:
 class _Session:
     """One admitted-or-evictable unit: a client's data set or one pattern chunk of it."""
 
-    def __init__(self, client, chunk, data: Dataset, precision, footprint):
+    def __init__(self, client, chunk, data: Dataset, precision, footprint, cost=0.0, tier=0):
         self.client = client
         self.chunk = chunk
         self.data = data
         self.precision = precision
         self.footprint = footprint
+        self.cost = cost           # estimated seconds per evaluation
+        self.tier = tier           # 0: small (its own batches, streams and slots), 1: large
         self.state = None          # executor's resident state (None: not on the device)
         self.key = None
         self.busy = False
@@ -318,11 +358,17 @@ class Server:
     memory_budget: bytes of device memory the sessions' workspaces may occupy (default: 85 %
     of the device's free memory at start-up); max_session_bytes: data sets whose workspace
     exceeds this are split into pattern chunks (default: a quarter of the budget).
+    small_seconds: sessions whose estimated evaluation time is below this are small (their
+    own tier); max_inflight_per_class / max_inflight_small: batches in flight per class and
+    tier (large / small); large_ratio: large sessions are batched only with sessions within
+    this factor of the oldest request's cost.
     """
 
     def __init__(self, device: int = 0, memory_budget: int | None = None,
                  max_session_bytes: int | None = None, max_batch: int = MAX_BATCH,
-                 max_inflight_per_class: int = 2, precision: dict | None = None, executor=None):
+                 max_inflight_per_class: int = 2, precision: dict | None = None, executor=None,
+                 small_seconds: float = 2e-3, max_inflight_small: int = 4, large_ratio: float = 2.0,
+                 max_chunk_seconds: float = 10e-3, min_chunk_patterns: int = 4096):
         self.ex = executor if executor is not None else HipExecutor(device)
         if memory_budget is None:
             memory_budget = int(0.85 * self.ex.free_memory())
@@ -332,6 +378,11 @@ class Server:
         self.max_session_bytes = int(max_session_bytes or self.memory_budget // 4)
         self.max_batch = max(1, min(int(max_batch), MAX_BATCH))
         self.max_inflight = max(1, int(max_inflight_per_class))
+        self.max_inflight_small = max(1, int(max_inflight_small))
+        self.small_seconds = float(small_seconds)
+        self.large_ratio = max(1.0, float(large_ratio))
+        self.max_chunk_seconds = float(max_chunk_seconds)
+        self.min_chunk_patterns = max(1, int(min_chunk_patterns))
         self.precision = dict(DEFAULT_PRECISION)
         self.precision.update(precision or {})
         self.sessions = {}                          # client -> [chunk sessions]
@@ -343,6 +394,7 @@ class Server:
         self.running = False
         self.thread = None
         self.latencies = []
+        self.latencies_small = []                   # requests whose every session is small
         self.completed = 0
         self.errors = 0
         self.batches = 0
@@ -360,6 +412,11 @@ class Server:
         prec = precision or self.precision.get(data.n_states, "bf16")
         full = self.ex.footprint(data, prec)
         n_chunks = max(1, -(-full // self.max_session_bytes))
+        # long evaluations are cut into chunks of about max_chunk_seconds, never below
+        # min_chunk_patterns patterns each
+        cost_full = self.ex.cost(data, prec) if hasattr(self.ex, "cost") else work_seconds(data, prec)
+        n_time = min(int(np.ceil(cost_full / self.max_chunk_seconds)), data.n_patterns // self.min_chunk_patterns)
+        n_chunks = max(n_chunks, n_time)
         if n_chunks > data.n_patterns:
             raise ValueError(f"client {client}: cannot chunk {data.n_patterns} patterns into {n_chunks}")
         bounds = np.linspace(0, data.n_patterns, n_chunks + 1).astype(int)
@@ -369,7 +426,8 @@ class Server:
             fp = full if n_chunks == 1 else self.ex.footprint(d, prec)
             if fp > self.memory_budget:
                 raise ValueError(f"client {client}: a pattern chunk does not fit the memory budget")
-            sess.append(_Session(client, c, d, prec, fp))
+            cost = self.ex.cost(d, prec) if hasattr(self.ex, "cost") else work_seconds(d, prec)
+            sess.append(_Session(client, c, d, prec, fp, cost, 0 if cost < self.small_seconds else 1))
         with self.cv:
             self.sessions[client] = sess
         return n_chunks
@@ -434,6 +492,7 @@ class Server:
         """Start a new measurement window (counters, latencies, throughput span)."""
         with self.cv:
             self.latencies = []
+            self.latencies_small = []
             self.completed = self.errors = self.batches = self.evictions = self.loads = 0
             self.load_seconds = self.evict_seconds = 0.0
             self.batch_sizes = []
@@ -442,6 +501,7 @@ class Server:
 
     def stats(self):
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        lat_s = np.array(self.latencies_small) if self.latencies_small else np.zeros(1)
         span = (self.t_last - self.t_first) if self.completed else 0.0
         return {"completed": self.completed, "errors": self.errors, "batches": self.batches,
                 "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
@@ -451,6 +511,9 @@ class Server:
                 "p50_ms": 1000 * float(np.percentile(lat, 50)),
                 "p99_ms": 1000 * float(np.percentile(lat, 99)),
                 "mean_ms": 1000 * float(np.mean(lat)),
+                "small_completed": len(self.latencies_small),
+                "small_p50_ms": 1000 * float(np.percentile(lat_s, 50)),
+                "small_p99_ms": 1000 * float(np.percentile(lat_s, 99)),
                 "requests_per_s": self.completed / span if span > 0 else float("nan"),
                 "memory_used": self.used, "memory_budget": self.memory_budget}
 
@@ -537,11 +600,18 @@ class Server:
         by_class = collections.defaultdict(list)
         for s in [s for s, q in self.pending.items() if q and not s.busy]:
             if self._admit(s):
-                by_class[s.key].append(s)
+                by_class[(s.key, s.tier)].append(s)
         for key, group in by_class.items():
-            if sum(1 for b in self.inflight if b[1] == key) >= self.max_inflight:
+            tier = key[1]
+            limit = self.max_inflight if tier else self.max_inflight_small
+            if sum(1 for b in self.inflight if b[1] == key) >= limit:
                 continue
             group.sort(key=lambda s: self.pending[s][0].arrival)
+            if tier:
+                # a batch of large sessions runs as long as its slowest member: only sessions
+                # within large_ratio of the oldest request's cost join it
+                c0 = group[0].cost
+                group = [s for s in group if c0 / self.large_ratio <= s.cost <= c0 * self.large_ratio]
             items = []
             for s in group[: self.max_batch]:
                 req = self.pending[s].popleft()
@@ -592,6 +662,8 @@ class Server:
                         out += req.parts[c]
                     req.future.set_result((float(out[0]), out[1:]))
                     self.latencies.append(now - req.arrival)
+                    if all(x.tier == 0 for x in self.sessions[req.client]):
+                        self.latencies_small.append(now - req.arrival)
                     self.completed += 1
                     self.t_first = req.arrival if self.t_first is None else min(self.t_first, req.arrival)
                     self.t_last = now

@@ -53,6 +53,10 @@ def simulate(plan, children):
                     pre[q2] = m2
                 grads += [g1, g2]
     assert sorted(grads) == list(range(2 * N - 2))
+    # the single-launch form of the backward pass is the same operations in the same order
+    flat = [([0] + list(r) + [0, 0, 0]) if kind == "post" else ([1] + list(r))
+            for kind, ops in plan.steps for r in ops]
+    assert np.array_equal(plan.mixed_ops, np.array(flat, dtype=np.int32).reshape(-1, 10))
     assert max(post) - N + 1 <= plan.n_post_buffers
     assert (max(pre) + 1 if pre else 1) <= plan.n_pre_buffers
 
@@ -127,27 +131,46 @@ class _SymbolicInstance:
 
     def pre_gradients_device(self, ops, acc):
         self.generation += 1
+        self._pre(ops, acc)
+        return acc
+
+    def _pre(self, ops, acc):
         for pp, c1, m1, q1, g1, c2, m2, q2, g2 in ops:
             for c, g in ((c1, g1), (c2, g2)):
                 v = self.post[c][1] if c >= self.n_tips else self.mats
                 self.read_versions.setdefault(int(g), set()).add(v)
                 acc[int(g)] += v
+
+    def traverse_gradients_device(self, ops, acc):
+        """The mixed list, in order: kind 0 a recomputation, kind 1 a pre-order operation."""
+        self.generation += 1
+        for row in ops:
+            if row[0] == 0:
+                dest, c1, m1, c2, m2, _ = row[1:7]
+                vs = {self.post[c][1] for c in (c1, c2) if c >= self.n_tips} | {self.mats}
+                assert len(vs) == 1, "a partial combined children of different evaluations"
+                self.post[int(dest)] = (int(m1), self.mats)
+            else:
+                self._pre([row[1:]], acc)
         return acc
 
 
-def _symbolic_checkpointed(n=40, period=3):
+def _symbolic_checkpointed(n=40, period=3, n_states=4):
+    """n_states 4 takes the backward pass as one mixed list, more states as step-wise calls."""
     from paper_2606_27607_amd.checkpoint import Checkpointed
     yule = synth.trees.yule_tree(n, np.random.default_rng(11)).children
     plan = CheckpointPlan(yule, period)
     inst = _SymbolicInstance(n, plan.n_post_buffers)
-    inst.desc = type("D", (), {"n_partials": plan.n_post_buffers, "n_pre_partials": plan.n_pre_buffers})
+    inst.desc = type("D", (), {"n_partials": plan.n_post_buffers, "n_pre_partials": plan.n_pre_buffers,
+                               "n_states": n_states})
     return Checkpointed(inst, plan), inst, 2 * n - 2
 
 
-def test_backward_after_a_second_forward_reads_its_own_evaluation():
+@pytest.mark.parametrize("n_states", [4, 61])
+def test_backward_after_a_second_forward_reads_its_own_evaluation(n_states):
     """Two forward passes, then the backward pass of the first: it must not read the second
     evaluation's partials or matrices (it runs the first forward pass again)."""
-    ck, inst, nb = _symbolic_checkpointed()
+    ck, inst, nb = _symbolic_checkpointed(n_states=n_states)
     t1, t2 = np.full(nb, 0.1), np.full(nb, 0.2)
     ck.lnl(t1)
     tok1, saved1 = ck.forward_token, ck.last_t
@@ -157,10 +180,11 @@ def test_backward_after_a_second_forward_reads_its_own_evaluation():
     assert np.allclose(g, 0.1)                          # each slot read once, at version 0.1
 
 
-def test_repeated_backward_reruns_the_forward_pass():
+@pytest.mark.parametrize("n_states", [4, 61])
+def test_repeated_backward_reruns_the_forward_pass(n_states):
     """A backward pass consumes the forward state: a second backward pass of the same
     forward call (retain_graph) runs the forward pass again, and gives the same values."""
-    ck, inst, nb = _symbolic_checkpointed(period=2)
+    ck, inst, nb = _symbolic_checkpointed(period=2, n_states=n_states)
     ck.lnl(np.full(nb, 0.3))
     tok, saved = ck.forward_token, ck.last_t
     g1 = ck.gradients(saved, tok)
@@ -173,12 +197,13 @@ def test_repeated_backward_reruns_the_forward_pass():
     ck.lnl(np.full(nb, 0.4))
     gen = inst.generation
     ck.gradients()
-    n_backward = len(ck.plan.steps)
+    n_backward = 1 if n_states <= 4 else len(ck.plan.steps)
     assert inst.generation == gen + n_backward
 
 
-def test_intervening_call_invalidates_the_forward_state():
-    ck, inst, nb = _symbolic_checkpointed()
+@pytest.mark.parametrize("n_states", [4, 61])
+def test_intervening_call_invalidates_the_forward_state(n_states):
+    ck, inst, nb = _symbolic_checkpointed(n_states=n_states)
     ck.lnl(np.full(nb, 0.5))
     tok, saved = ck.forward_token, ck.last_t
     inst.update_matrices(np.arange(nb), np.full(nb, 0.9))   # any other use of the instance

@@ -86,3 +86,56 @@ def test_checkpoint_autograd_mode():
     lnl_o, _, g_o = oracle_eval(wl)
     assert rel(out.item(), lnl_o) < 1e-12
     assert grad_err(t.grad.cpu().numpy() / 3.0, g_o) < 1e-9
+
+
+@pytest.mark.parametrize("precision,period", [("f64", 3), ("f32", 4), ("f32", 1000)])
+def test_one_launch_backward_equals_stepwise_calls(precision, period):
+    """For four states the backward pass runs as one mixed list (hp_traverse_gradients_device);
+    the same operations as step-wise hp_update_post / hp_pre_gradients_device calls give
+    bitwise the same gradients, and one launch is all the backward pass issues."""
+    wl = synth.make_workload("gtr", 70, 3000, seed=[20260075, period], unknown_frac=0.02)
+    ck = checkpointed(wl, period, precision, "every_k", 4)
+    nb = 2 * wl.n_tips - 2
+    ck.lnl(wl.t)
+    inst = ck.inst
+    inst.profile(True)
+    inst.profile_read()
+    g_one = ck.gradients()
+    prof = inst.profile_read()
+    inst.profile(False)
+    assert prof["traversal"][1] == 1 and prof["reduce"][1] == 1, prof
+    ck.lnl(wl.t)
+    acc = torch.zeros(nb, dtype=torch.float64, device=inst.device)
+    for kind, ops in ck.plan.steps:
+        if kind == "post":
+            inst.update_post(ops)
+        else:
+            inst.pre_gradients_device(ops, acc)
+    g_steps = acc.cpu().numpy()
+    assert np.array_equal(g_one, g_steps), np.max(np.abs(g_one - g_steps))
+    lnl_o, _, g_o = oracle_eval(wl)
+    check(ck.lnl(wl.t), lnl_o, g_one, g_o, precision, wl.n_states, what="one-launch backward")
+
+
+def test_mixed_list_validation():
+    """Entries are validated as the operations they hold: a bad kind, a bad buffer and a
+    repeated gradient slot are refused before anything runs."""
+    from paper_2606_27607_amd import HPError, _lib
+    wl = synth.make_workload("hky", 10, 200, seed=5)
+    ck = checkpointed(wl, 2, "f64", "every_k", 2)
+    ck.lnl(wl.t)
+    acc = torch.zeros(2 * wl.n_tips - 2, dtype=torch.float64, device=ck.inst.device)
+    good = ck.plan.mixed_ops
+    for mutate, code in ((lambda o: o.__setitem__((0, 0), 2), _lib.HP_ERR_ARG),
+                         (lambda o: o.__setitem__((0, 1), 10 ** 6), _lib.HP_ERR_INDEX)):
+        bad = good.copy()
+        mutate(bad)
+        with pytest.raises(HPError) as e:
+            ck.inst.traverse_gradients_device(bad, acc)
+        assert e.value.code == code
+    pre_rows = np.nonzero(good[:, 0] == 1)[0]
+    bad = good.copy()
+    bad[pre_rows[1], 5] = bad[pre_rows[0], 5]        # the same gradient slot twice
+    with pytest.raises(HPError) as e:
+        ck.inst.traverse_gradients_device(bad, acc)
+    assert e.value.code == _lib.HP_ERR_ARG

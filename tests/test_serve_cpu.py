@@ -13,8 +13,11 @@ from paper_2606_27607_amd.serve import Arena, Dataset, Server
 
 class FakeExecutor:
     def __init__(self, service_s=0.002, fail_clients=(), raise_on_launch=(), raise_on_load=(),
-                 raise_on_poll=0, arena_bytes=None):
+                 raise_on_poll=0, arena_bytes=None, cost_per_pattern=None):
         self.service_s = service_s
+        # with cost_per_pattern, a session's estimated cost (and a batch's service time, that
+        # of its slowest member) is proportional to its pattern count
+        self.cost_per_pattern = cost_per_pattern
         self.fail_clients = set(fail_clients)
         self.raise_on_launch = set(raise_on_launch)
         self.raise_on_load = set(raise_on_load)
@@ -32,6 +35,9 @@ class FakeExecutor:
 
     def footprint(self, data, precision):
         return data.n_tips * data.n_patterns * 8
+
+    def cost(self, data, precision):
+        return (self.cost_per_pattern or 1e-9) * data.n_patterns
 
     def load(self, s):
         if s.client in self.raise_on_load:
@@ -60,6 +66,8 @@ class FakeExecutor:
         for s, _ in items:
             assert s in self.resident
         self.launches.append([s.client for s, _ in items])
+        if self.cost_per_pattern:
+            return (time.perf_counter() + max(s.cost for s, _ in items), items)
         return (time.perf_counter() + self.service_s, items)
 
     def poll(self, token):
@@ -256,3 +264,61 @@ def test_fragmented_memory_evicts_until_a_range_fits():
         assert srv.evaluate(3, np.full(8, 0.1))[0] == pytest.approx(0.8 * 400)
         st = srv.stats()
     assert st["evictions"] >= 2 and ex.max_used <= 10 * unit
+
+
+def test_small_requests_never_wait_behind_a_large_one():
+    """One large evaluation of a class in flight (its only large slot taken) and small
+    requests of the same class arriving after it: they run in their own tier and finish
+    long before it, batched with each other."""
+    ex = FakeExecutor(cost_per_pattern=2e-6)                  # 100,000 patterns: 0.2 s
+    with Server(memory_budget=10 ** 9, executor=ex, max_inflight_per_class=1,
+                small_seconds=2e-3, max_inflight_small=2, max_chunk_seconds=10.0) as srv:
+        srv.register(0, dataset(8, 100_000))
+        for c in range(1, 9):
+            srv.register(c, dataset(6, 200))                  # 0.4 ms each
+        big = srv.submit(0, np.ones(14))
+        time.sleep(0.01)
+        smalls = [srv.submit(c, np.ones(10)) for c in range(1, 9)]
+        for f in smalls:
+            f.result(timeout=5)
+        assert not big.done()
+        big.result(timeout=5)
+        st = srv.stats()
+    assert st["small_completed"] == 8 and st["small_p99_ms"] < 100
+    small_batches = [b for b in ex.launches if 0 not in b]
+    assert len(small_batches) < 8                             # they shared launches
+
+
+def test_large_sessions_batch_only_with_similar_costs():
+    """Large sessions whose costs differ by more than large_ratio never share a batch (a batch
+    runs as long as its slowest member); similar ones do."""
+    ex = FakeExecutor(cost_per_pattern=1e-7)
+    with Server(memory_budget=10 ** 10, executor=ex, small_seconds=1e-3, large_ratio=2.0,
+                max_inflight_per_class=1, max_chunk_seconds=10.0) as srv:
+        sizes = {0: 50_000, 1: 60_000, 2: 400_000, 3: 450_000}   # 5, 6, 40 and 45 ms
+        for c, n in sizes.items():
+            srv.register(c, dataset(6, n))
+        for rep in range(3):
+            futs = [srv.submit(c, np.full(10, 0.1 * (rep + 1))) for c in sizes]
+            for f in futs:
+                f.result(timeout=10)
+    for b in ex.launches:
+        costs = [sizes[c] for c in b]
+        assert max(costs) <= 2.0 * min(costs), b
+    assert any(len(b) > 1 for b in ex.launches)
+
+
+def test_long_evaluations_are_cut_into_time_chunks():
+    """A data set estimated at 0.2 s per evaluation becomes 20 pattern chunks of ~10 ms (each at
+    least min_chunk_patterns patterns); one whose chunks would fall below that minimum stays
+    whole.  Results are the chunk sums, as for memory chunking."""
+    ex = FakeExecutor(cost_per_pattern=2e-6)
+    with Server(memory_budget=10 ** 12, executor=ex, max_chunk_seconds=10e-3, min_chunk_patterns=4096) as srv:
+        assert srv.register(0, dataset(8, 100_000)) == 20
+        assert srv.register(1, dataset(8, 6_000)) == 1            # 12 ms, but 6,000 < 2 x 4,096
+        assert srv.register(2, dataset(8, 9_000)) == 2
+        for c, n in ((0, 100_000), (1, 6_000), (2, 9_000)):
+            t = np.linspace(0.01, 0.1, 14)
+            lnl, g = srv.evaluate(c, t)
+            e_l, e_g = expected(t, n)
+            assert np.isclose(lnl, e_l, rtol=1e-12) and np.allclose(g, e_g, rtol=1e-12)
