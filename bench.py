@@ -694,6 +694,9 @@ def main():
                          "spaces, Poisson arrivals), which runs by default")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving benchmark")
     ap.add_argument("--serving-clients", type=int, default=64)
+    ap.add_argument("--autograd-only", action="store_true",
+                    help="run only the differentiation legs (nuc256 FP32, codon32 BF16: store, "
+                         "recompute, fused and checkpoint modes)")
     ap.add_argument("--eig-only", metavar="PRECISIONS",
                     help="run only the eigensystem-path leg (geo200), e.g. f64 or f64,f32")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -717,6 +720,11 @@ def main():
 
     import synth
 
+    if args.autograd_only:
+        print(json.dumps({"autograd": [measure_autograd(synth.config_workload("nuc256"), "f32", args.steps),
+                                       measure_autograd(synth.config_workload("codon32"), "bf16", args.steps)]}),
+              flush=True)
+        return
     if args.eig_only:
         geo = synth.geo_workload()
         print(json.dumps({"eigensystem_path": [measure_eig(geo, p, max(10, args.steps // 4), 3)

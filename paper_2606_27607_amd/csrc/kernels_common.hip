@@ -87,26 +87,45 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
     const size_t base = (size_t)(m * K + k) * S_pad * S_pad;
     T* Pm = mats + base;
     T* Tt = static_cast<T*>(d.tiptab) + (size_t)(m * K + k) * (S + 1) * S_pad;
-    for (int e = threadIdx.x; e < S_pad * S_pad; e += blockDim.x) {
-        const int x = e / S_pad, y = e % S_pad;
-        double v = 0.0;
-        if (x < S && y < S)
-            for (int j = 0; j < S; ++j) v += VL[x * S + j] * W[j * S + y];
-        if (bad) v = NAN;
-        Pm[e] = T(v);
-        if (y < S) Tt[y * S_pad + x] = T(v);
-        if (matsT) matsT[base + (size_t)y * S_pad + x] = T(v);
-        if (m16) {
-            const float c = v > 0.0 ? float(v) : (bad ? float(v) : 0.0f);
-            const H hi = H(c);
-            m16[base + e] = hi;
-            mT16[base + (size_t)y * S_pad + x] = hi;
-            if (d.lo_off) {
-                const H lo = H(c - float(hi));
-                m16[d.lo_off + base + e] = lo;
-                mT16[d.lo_off + base + (size_t)y * S_pad + x] = lo;
+    // each thread forms a 4 x 4 block of P, so that every LDS value it reads serves four
+    // products (each entry's sum still runs over j in order, as one entry per thread did)
+    const int nb4 = S_pad / 4;
+    for (int blk = threadIdx.x; blk < nb4 * nb4; blk += blockDim.x) {
+        const int x0 = 4 * (blk / nb4), y0 = 4 * (blk % nb4);
+        double v[4][4] = {};
+        for (int j = 0; j < S; ++j) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                av[r] = x0 + r < S ? VL[(x0 + r) * S + j] : 0.0;
+                bv[r] = y0 + r < S ? W[j * S + y0 + r] : 0.0;
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[r][c] += av[r] * bv[c];
         }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int x = x0 + r, y = y0 + c, e = x * S_pad + y;
+                const double pv = (x < S && y < S) ? (bad ? NAN : v[r][c]) : (bad ? NAN : 0.0);
+                Pm[e] = T(pv);
+                if (y < S) Tt[y * S_pad + x] = T(pv);
+                if (matsT) matsT[base + (size_t)y * S_pad + x] = T(pv);
+                if (m16) {
+                    const float cf = pv > 0.0 ? float(pv) : (bad ? float(pv) : 0.0f);
+                    const H hi = H(cf);
+                    m16[base + e] = hi;
+                    mT16[base + (size_t)y * S_pad + x] = hi;
+                    if (d.lo_off) {
+                        const H lo = H(cf - float(hi));
+                        m16[d.lo_off + base + e] = lo;
+                        mT16[d.lo_off + base + (size_t)y * S_pad + x] = lo;
+                    }
+                }
+            }
     }
     for (int x = threadIdx.x; x < S_pad; x += blockDim.x) {
         double v = 0.0;
@@ -131,6 +150,23 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
 template <typename T, typename H, int SMAX>
 __global__ void __launch_bounds__(256) pmat_kernel(const PmatDev d, const double* __restrict__ t) {
     pmat_body<T, H, SMAX>(d, blockIdx.x, blockIdx.y, t[blockIdx.x]);
+}
+
+// Four states: one thread per (matrix, category), 256 to a workgroup (pmat4, the arithmetic of
+// pmat_body's four-state branch, so both give the same bits).
+template <typename T>
+__global__ void __launch_bounds__(256) pmat4_kernel(const PmatDev d, const double* __restrict__ t, int count) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int K = d.K, S = d.S;
+    if (q >= count * K) return;
+    const int i = q / K, k = q % K;
+    const int m = d.idx ? d.idx[i] : i;
+    const double tt = t[i];
+    const bool bad = !(tt >= 0.0) || isinf(tt);
+    if (bad) atomicOr(d.status, kStatusValue);
+    pmat4<T, const double*>(d.eig, d.eig + S * S, d.eig + 2 * S * S, d.cat_r[k] * tt, bad, S,
+                            static_cast<T*>(d.mats) + (size_t)(m * K + k) * 16,
+                            static_cast<T*>(d.tiptab) + (size_t)(m * K + k) * (S + 1) * 4);
 }
 
 template <typename T, typename H, int SMAX>
@@ -254,6 +290,14 @@ hipError_t launch_pmat(const Instance& I, int eigen_idx, const int32_t* d_idx, c
                        int count) {
     if (count <= 0) return hipSuccess;
     const PmatDev d = build_pmat_desc(I, eigen_idx, d_idx);
+    if (I.S_pad == 4) {
+        const int n = count * I.d.n_categories;
+        if (I.d.precision == HP_PREC_F64)
+            hipLaunchKernelGGL((pmat4_kernel<double>), dim3((n + 255) / 256), dim3(256), 0, I.stream, d, d_t, count);
+        else
+            hipLaunchKernelGGL((pmat4_kernel<float>), dim3((n + 255) / 256), dim3(256), 0, I.stream, d, d_t, count);
+        return hipGetLastError();
+    }
     pmat_dispatch<LaunchPmat>(I, dim3(count, I.d.n_categories), d, d_t);
     return hipGetLastError();
 }
