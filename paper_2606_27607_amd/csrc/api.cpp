@@ -258,7 +258,8 @@ int compute_layout(const hp_desc& d, int* S_pad_out, int* P_pad_out, int* elem_o
     l.t_stage = take(nm * 8);
     l.idx_stage = take(nm * 4);
     l.ops_stage = take((size_t)max_ops(d) * kPreOpInts * 4);
-    l.tree_ops = take((size_t)(d.n_tips) * (kPostOpInts + kPreOpInts) * 4);
+    // the whole-tree lists: post-order, pre-order, then the matrix-core walk's product list
+    l.tree_ops = take((size_t)(d.n_tips) * (kPostOpInts + kPreOpInts + kProdPerTip) * 4);
     l.partials = take((size_t)l.max_out * n_blocks * 8);
     l.results = take((size_t)l.max_out * 8);
     l.status = take(64);
@@ -1202,6 +1203,13 @@ int hp_set_tree(hp_instance* inst, const int32_t* children) {
     if (rc) return rc;
     rc = upload(I, dst + (size_t)(N - 1) * hp::kPostOpInts, pre.data(), pre.size() * 4);
     if (rc) return rc;
+    std::vector<int32_t> prod;
+    int n_prod_post = 0;
+    hp::tree_products(N, post, pre, &prod, &n_prod_post);
+    rc = upload(I, dst + (size_t)(N - 1) * (hp::kPostOpInts + hp::kPreOpInts), prod.data(), prod.size() * 4);
+    if (rc) return rc;
+    I->tree_n_prod = (int)prod.size();
+    I->tree_n_prod_post = n_prod_post;
     // whole-tree kernel descriptors for batched evaluation: traversal with gradients,
     // traversal without, matrix assembly (branch c uses matrix slot c)
     std::vector<unsigned char> desc(3 * hp::kDescBytes, 0);

@@ -41,6 +41,7 @@ enum WalkMode : int {
     kFusedLds = 256,  // with kFused: the partial buffers in LDS too
     kMixed = 512,     // 4-state walk of one list mixing post- and pre-order operations (with kGrad)
 };
+constexpr int kProdPerTip = 3;     // product-list entries per tip (at most 3 N - 6 products)
 constexpr int kMixedOpInts = 10;   // kind (0 post, 1 pre), then the hp_post_op / hp_pre_op fields
 constexpr int kQSlots = 16;        // reduction slots of the rate-matrix gradient (S_pad^2, S <= 4)
 
@@ -174,6 +175,7 @@ struct Instance {
     bool tree_set = false;
     int tree_n_post = 0, tree_n_pre = 0;
     int tree_pre_bufs = 0;          // pre-order buffers the whole-tree lists use
+    int tree_n_prod = 0, tree_n_prod_post = 0;   // the product list (tree_products)
     double* host_out = nullptr;     // pinned host buffer for results
     int32_t* host_status = nullptr; // pinned
     // pinned host staging of the per-call uploads (operation lists, matrix indices, branch
@@ -193,6 +195,15 @@ struct Instance {
 constexpr bool mfma16(int prec) { return prec == HP_PREC_BF16 || prec == HP_PREC_F16 || prec == HP_PREC_BF16X3; }
 // ... of which these also keep a lo BF16 part of every matrix entry.
 constexpr bool bf16_split(int prec) { return prec == HP_PREC_BF16 || prec == HP_PREC_BF16X3; }
+
+// Column order of the 16-bit copies of P and P^T (rows unchanged).  A 16-bit MFMA step takes
+// from lane group g the contraction values 4g..4g+3 and 16+4g..16+4g+3 of a 32-column block
+// (the order of the partials' R2 rows); storing each block's columns as
+// [0-3, 16-19, 4-7, 20-23, 8-11, 24-27, 12-15, 28-31] makes a lane's eight values one
+// contiguous 16-byte load, at column 32 s + 8 g, which a direct load into LDS can also fetch.
+__host__ __device__ constexpr int mcol16(int y) {
+    return (y & ~31) + 8 * ((y & 15) >> 2) + 4 * ((y & 31) >> 4) + (y & 3);
+}
 
 // Host-side round-to-nearest-even conversions for the 16-bit copies of Q.
 inline uint16_t to_bf16_bits(double v) {
@@ -263,6 +274,25 @@ size_t fused_small_lds_bytes(const Instance& I, int n_pre_buf, bool partials);
 hipError_t launch_fused_small(const Instance& I, const FusedLaunch& L);
 // Size in bytes of the traversal descriptor for whole-tree evaluation, written to host_buf.
 size_t build_tree_desc(const Instance& I, int want_grad, void* host_buf);
+// The matrix products of the matrix-core whole-tree walk in the order it forms them, 2 m + t
+// for matrix slot m (t = 0: P, t = 1: P^T): P of every post-order operation but the root's,
+// then per pre-order operation P^T of each child that gets a pre-order partial, the child the
+// walk takes first (a tip child of an operation with one tip child, else the first listed)
+// first.  The walk prefetches each product's matrix into LDS during the one before it and
+// checks the slot it prefetched, so the list decides speed, never results.
+inline void tree_products(int N, const std::vector<int32_t>& post, const std::vector<int32_t>& pre,
+                          std::vector<int32_t>* prod, int* n_post_products) {
+    prod->clear();
+    const int n_post = (int)post.size() / kPostOpInts, n_pre = (int)pre.size() / kPreOpInts;
+    for (int i = 0; i + 1 < n_post; ++i) prod->push_back(2 * post[(size_t)i * kPostOpInts]);
+    *n_post_products = (int)prod->size();
+    for (int i = 0; i < n_pre; ++i) {
+        const int32_t* op = pre.data() + (size_t)i * kPreOpInts;
+        const int o1 = op[1] >= N && op[5] < N ? 5 : 1, o2 = 6 - o1;
+        if (op[o1 + 2] >= 0) prod->push_back(2 * op[o1 + 1] + 1);
+        if (op[o2 + 2] >= 0) prod->push_back(2 * op[o2 + 1] + 1);
+    }
+}
 PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx);
 hipError_t launch_batch(const Instance& first, const BatchArgs& b, int want_grad);
 // Whole-tree evaluation on the eigensystem path (everything but the final pattern reduction).

@@ -18,8 +18,8 @@ namespace {
 //   tiptab[m][k][S][x]      = sum_y P[x][y]         the propagated all-ones (unknown) tip
 // A negative or non-finite t raises kStatusValue and writes NaN.
 // Matrix-core path extras (null when unused): matsT[m][k][y][x] = P[x][y] in T, and 16-bit
-// copies of P and P^T in H (negative rounding residues clamped to 0 before the cast); for
-// BF16 a lo part (value - hi) follows lo_off elements later.
+// copies of P and P^T in H (negative rounding residues clamped to 0 before the cast), their
+// columns in the order mcol16; for BF16 a lo part (value - hi) follows lo_off elements later.
 // With the Q . post cache (qptab not null): qptab[m][k][s][x] = (Q P)[x][s] (s < S), the
 // propagated one-hot tip under Q, from V diag(lam exp(lam r t)) Vinv; column S (the unknown
 // tip) is Q 1 = 0 exactly.
@@ -117,12 +117,13 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
                 if (m16) {
                     const float cf = pv > 0.0 ? float(pv) : (bad ? float(pv) : 0.0f);
                     const H hi = H(cf);
-                    m16[base + e] = hi;
-                    mT16[base + (size_t)y * S_pad + x] = hi;
+                    const size_t e16 = (size_t)x * S_pad + mcol16(y), eT16 = (size_t)y * S_pad + mcol16(x);
+                    m16[base + e16] = hi;
+                    mT16[base + eT16] = hi;
                     if (d.lo_off) {
                         const H lo = H(cf - float(hi));
-                        m16[d.lo_off + base + e] = lo;
-                        mT16[d.lo_off + base + (size_t)y * S_pad + x] = lo;
+                        m16[d.lo_off + base + e16] = lo;
+                        mT16[d.lo_off + base + eT16] = lo;
                     }
                 }
             }
@@ -152,10 +153,11 @@ __global__ void __launch_bounds__(256) pmat_kernel(const PmatDev d, const double
     pmat_body<T, H, SMAX>(d, blockIdx.x, blockIdx.y, t[blockIdx.x]);
 }
 
-// Four states: one thread per (matrix, category), 256 to a workgroup (pmat4, the arithmetic of
-// pmat_body's four-state branch, so both give the same bits).
+// Four states: one thread per (matrix, category), 64 to a workgroup so that a few hundred
+// matrices spread over as many compute units (pmat4, the arithmetic of pmat_body's four-state
+// branch, so both give the same bits).
 template <typename T>
-__global__ void __launch_bounds__(256) pmat4_kernel(const PmatDev d, const double* __restrict__ t, int count) {
+__global__ void __launch_bounds__(64) pmat4_kernel(const PmatDev d, const double* __restrict__ t, int count) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int K = d.K, S = d.S;
     if (q >= count * K) return;
@@ -293,9 +295,9 @@ hipError_t launch_pmat(const Instance& I, int eigen_idx, const int32_t* d_idx, c
     if (I.S_pad == 4) {
         const int n = count * I.d.n_categories;
         if (I.d.precision == HP_PREC_F64)
-            hipLaunchKernelGGL((pmat4_kernel<double>), dim3((n + 255) / 256), dim3(256), 0, I.stream, d, d_t, count);
+            hipLaunchKernelGGL((pmat4_kernel<double>), dim3((n + 63) / 64), dim3(64), 0, I.stream, d, d_t, count);
         else
-            hipLaunchKernelGGL((pmat4_kernel<float>), dim3((n + 255) / 256), dim3(256), 0, I.stream, d, d_t, count);
+            hipLaunchKernelGGL((pmat4_kernel<float>), dim3((n + 63) / 64), dim3(64), 0, I.stream, d, d_t, count);
         return hipGetLastError();
     }
     pmat_dispatch<LaunchPmat>(I, dim3(count, I.d.n_categories), d, d_t);
