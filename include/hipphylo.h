@@ -312,9 +312,11 @@ int hp_plan_pre_buffers(int n_tips, const int32_t* children, int* out_count);
  * root integration, and, if want_grad, pre-order partials and all 2N-2 branch gradients.
  * Host pointers; blocking.  grad may be NULL when want_grad == 0.  A small 4-state problem
  * with gradients (at most 64 taxa and 64 workgroups of 64 patterns, its matrices fitting one
- * workgroup's LDS) runs as one kernel launch that takes t by value and writes the results
- * straight to pinned host memory, bitwise equal to the three-launch form; it then leaves no
- * partials or matrices in the workspace. */
+ * workgroup's LDS) runs as one kernel launch that takes t by value; each workgroup writes its
+ * pattern sums and then its own status word to pinned host memory, and the call returns once
+ * every workgroup's word has arrived, after adding the sums on the host in the fixed order of
+ * the reduction kernel (bitwise equal to the three-launch form).  It leaves no partials or
+ * matrices in the workspace and neither reads nor clears the device status word. */
 int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_lnl,
                 double* out_grad);
 

@@ -8,6 +8,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
+#include <chrono>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -523,6 +525,7 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
         std::string m = I->err;
         if (I->host_out) (void)hipHostFree(I->host_out);
         if (I->host_status) (void)hipHostFree(I->host_status);
+        if (I->host_rows) (void)hipHostFree(I->host_rows);
         free_staging(I);
         delete I;
         g_create_error = m;
@@ -541,6 +544,14 @@ int hp_create(const hp_desc* desc, void* dev_workspace, size_t workspace_bytes, 
     if (hipHostMalloc(reinterpret_cast<void**>(&I->host_out), (size_t)I->L.max_out * 8) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&I->host_status), 64) != hipSuccess)
         return cleanup(fail(I, HP_ERR_DEVICE, "hipHostMalloc of the result staging buffer failed"));
+    if (I->S_pad == 4 && I->n_blocks <= hp::kFusedMaxBlocks) {
+        const size_t rows = (size_t)I->L.max_out * I->n_blocks * 8;
+        void* p = nullptr;
+        if (hipHostMalloc(&p, rows + (size_t)I->n_blocks * 4) != hipSuccess)
+            return cleanup(fail(I, HP_ERR_DEVICE, "hipHostMalloc of the one-launch reduction rows failed"));
+        I->host_rows = static_cast<double*>(p);
+        I->host_wg_status = reinterpret_cast<int32_t*>(static_cast<uint8_t*>(p) + rows);
+    }
     I->stage_bytes = std::max({(size_t)max_ops(*desc) * std::max(sizeof(hp_post_op), sizeof(hp_pre_op)),
                                (size_t)desc->n_matrices * 8, (size_t)(2 * desc->n_tips) * 8});
     for (int s = 0; s < Instance::kStageSlots; ++s) {
@@ -575,6 +586,7 @@ int hp_destroy(hp_instance* inst) {
         for (hipEvent_t e : I->prof.ev) (void)hipEventDestroy(e);
         if (I->host_out) (void)hipHostFree(I->host_out);
         if (I->host_status) (void)hipHostFree(I->host_status);
+        if (I->host_rows) (void)hipHostFree(I->host_rows);
         free_staging(I);
     }
     delete I;
@@ -1293,6 +1305,41 @@ int enqueue_evaluate(Instance* I, const double* d_t, int want_grad, double* d_ou
 extern "C" {
 using hp::enqueue_evaluate;
 
+// The sum reduce_rows forms of one row of at most 64 workgroup partials (thread t holds
+// 0 + partial t, a shuffle tree takes lane l to s_l + s_(l xor o) for o = 32 .. 1, then the
+// other three waves' zeros are added in order), on the host: the same FP64 operations in the
+// same order, so the same bits.
+static double sum_rows_fixed(const double* row, int n) {
+    double v[64], w[64];
+    for (int l = 0; l < 64; ++l) v[l] = l < n ? 0.0 + row[l] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+        for (int l = 0; l < 64; ++l) w[l] = v[l] + v[l ^ o];
+        std::copy(w, w + 64, v);
+    }
+    return ((v[0] + 0.0) + 0.0) + 0.0;
+}
+
+// Wait until every workgroup of a one-launch evaluation has written its status word (>= 0)
+// to pinned host memory, spinning for up to 2 ms and then on the stream (which also reports
+// a failed kernel); its rows are visible once its word is.
+static int wait_workgroups(Instance* I, volatile int32_t* wg, int n) {
+    auto all = [&]() {
+        for (int b = 0; b < n; ++b)
+            if (wg[b] < 0) return false;
+        return true;
+    };
+    const auto t0 = std::chrono::steady_clock::now();
+    while (!all()) {
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+            HP_HIP(I, hipStreamSynchronize(I->stream));
+            if (!all()) return fail(I, HP_ERR_DEVICE, "one-launch evaluation ended without its status words");
+            break;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return HP_OK;
+}
+
 static int check_eval_state(Instance* I) {
     if (!I->tree_set) return fail(I, HP_ERR_STATE, "hp_set_tree was not called");
     if (!I->eigen_set[0]) return fail(I, HP_ERR_STATE, "eigensystem 0 not set");
@@ -1311,18 +1358,28 @@ int hp_evaluate(hp_instance* inst, const double* t, int want_grad, double* out_l
         if (!(t[c] >= 0.0) || !std::isfinite(t[c])) return fail(I, HP_ERR_VALUE, "branch length < 0 or not finite");
     DeviceGuard g(I->d.device);
     const int n_out = want_grad ? 1 + nb : 1;
-    if (hp::fused_eligible(I, want_grad)) {
-        // one launch: branch lengths by value, results and the taken status word written by
-        // the kernel straight into the pinned host buffers, one wait
+    if (hp::fused_eligible(I, want_grad) && I->host_rows) {
+        // one launch: branch lengths by value; every workgroup writes its reduction rows and
+        // then its status word to pinned host memory, and the host, once each workgroup's
+        // word has arrived, adds the rows in the fixed order of the reduction kernel
         hp::FusedLaunch L = hp::fused_launch(I, want_grad);
         L.t_host = t;
-        L.out = I->host_out;
-        L.out_status = I->host_status;
+        L.host_rows = I->host_rows;
+        L.host_wg_status = I->host_wg_status;
+        const int nwg = L.n_blocks;
+        volatile int32_t* wg = I->host_wg_status;
+        for (int b = 0; b < nwg; ++b) wg[b] = -1;
         HP_HIP(I, timed(I, hp::kTraversal, [&] { return hp::launch_fused_small(*I, L); }));
-        HP_HIP(I, hipStreamSynchronize(I->stream));
-        *out_lnl = I->host_out[0];
-        if (want_grad) std::copy(I->host_out + 1, I->host_out + n_out, out_grad);
-        if (*I->host_status & hp::kStatusNumeric) {
+        rc = wait_workgroups(I, wg, nwg);
+        if (rc) return rc;
+        int32_t st = 0;
+        for (int b = 0; b < nwg; ++b) st |= wg[b];
+        for (int j = 0; j < n_out; ++j) {
+            const double v = sum_rows_fixed(I->host_rows + (size_t)j * nwg, nwg);
+            if (j == 0) *out_lnl = v;
+            else out_grad[j - 1] = v;
+        }
+        if (st & hp::kStatusNumeric) {
             *out_lnl = -INFINITY;
             return fail(I, HP_ERR_NUMERIC, "a site likelihood was zero or not finite");
         }

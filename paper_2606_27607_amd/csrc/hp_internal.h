@@ -178,6 +178,10 @@ struct Instance {
     int tree_n_prod = 0, tree_n_prod_post = 0;   // the product list (tree_products)
     double* host_out = nullptr;     // pinned host buffer for results
     int32_t* host_status = nullptr; // pinned
+    // pinned: the one-launch evaluation's reduction rows [max_out][n_blocks], then one status
+    // word per workgroup (4-state instances of at most kFusedMaxBlocks workgroups)
+    double* host_rows = nullptr;
+    int32_t* host_wg_status = nullptr;
     // pinned host staging of the per-call uploads (operation lists, matrix indices, branch
     // lengths): a ring of slots, each reused once the copy that last read it has completed
     static constexpr int kStageSlots = 4;
@@ -268,6 +272,8 @@ struct FusedLaunch {
     int32_t* counter = nullptr;
     int n_blocks = 0, n_pre_buf = 0;
     bool lds_partials = false;         // partial buffers in LDS too, where they fit
+    double* host_rows = nullptr;       // or null: reduction rows per workgroup to pinned host
+    int32_t* host_wg_status = nullptr; // memory, and each workgroup's status word after them
 };
 // LDS bytes of one workgroup: matrices and tip tables, and the partial buffers if `partials`.
 size_t fused_small_lds_bytes(const Instance& I, int n_pre_buf, bool partials);

@@ -147,6 +147,8 @@ struct FusedLds {
     T* post = nullptr;       // [n_post][K][kWave][4]
     T* pre = nullptr;        // [n_pre][K][kWave][4]
     int32_t* pexp = nullptr; // [n_post][kWave]
+    double* partials = nullptr;   // reduction rows [n_out][n_blocks] (device or pinned host)
+    int32_t* status = nullptr;    // status word (device, or the workgroup's own in LDS)
 };
 
 template <typename T, int KMAX, int PPL, int MODE>
@@ -163,10 +165,13 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
     const int p0 = block * TW + lane;
     const int K = a.K;
     int sb = 0;  // exchange counter: consecutive LDS exchanges alternate buffers
+    // the one-launch evaluation may send its reduction rows and status elsewhere
+    double* const part = kF ? fl.partials : a.h.partials;
+    int32_t* const status = kF ? fl.status : a.status;
 
     if (MODE & (kRootFused | kRootBuf | kGrad)) {
         for (int j = threadIdx.x; j < a.h.n_out; j += blockDim.x)
-            a.h.partials[(size_t)j * a.h.n_blocks + block] = 0.0;
+            part[(size_t)j * a.h.n_blocks + block] = 0.0;
         __syncthreads();
     }
 
@@ -185,7 +190,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 const double L = cat_sum(sh_v[s][0], K, lane + j * kWave);
                 double l = log(L) + double(E[j]) * 0.69314718055994530942;
                 if (!(L > 0.0) || !isfinite(l)) {
-                    atomicOr(a.status, kStatusNumeric);
+                    atomicOr(status, kStatusNumeric);
                     l = -INFINITY;
                 }
                 if (a.site) a.site[p] = l;
@@ -193,7 +198,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 tot += w == 0.0 ? 0.0 : w * l;
             }
             tot = wave_sum(tot);
-            if (lane == 0) a.h.partials[block] = tot;
+            if (lane == 0) part[block] = tot;
         }
     };
 
@@ -398,7 +403,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                             tot += cp[j] == 0.0 ? 0.0 : cp[j] * r;
                         }
                         tot = wave_sum(tot);
-                        if (lane == 0) a.h.partials[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
+                        if (lane == 0) part[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
                     }
                 }
             }
@@ -612,7 +617,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                             tot += cp[j] == 0.0 ? 0.0 : cp[j] * r;
                         }
                         tot = wave_sum(tot);
-                        if (lane == 0) a.h.partials[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
+                        if (lane == 0) part[(size_t)(1 + g) * a.h.n_blocks + block] = tot;
                     }
                     if constexpr ((MODE & kQGrad) != 0) {
                         // every wave needs each pattern's category sum of the denominator
@@ -678,7 +683,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 const int x = threadIdx.x / a.S, y = threadIdx.x % a.S;
                 double v = 0.0;
                 for (int kk = 0; kk < K; ++kk) v += sh_q[kk][4 * x + y];
-                a.h.partials[(size_t)(a.q_slot + threadIdx.x) * a.h.n_blocks + block] = v;
+                part[(size_t)(a.q_slot + threadIdx.x) * a.h.n_blocks + block] = v;
             }
         }
     }
@@ -727,6 +732,8 @@ struct FusedArgs {
     double* out;             // 1 + n_grad results (device or pinned host memory)
     int32_t* out_status;     // null, or where the taken status word goes (pinned host)
     int32_t* counter;        // workgroups finished; zero between launches
+    double* host_rows;       // or null: each workgroup's reduction rows, [n_out][n_blocks], and
+    int32_t* host_wg_status; // its status word, to pinned host memory (no last workgroup)
     int n_mat, n_post_buf, n_pre_buf;
     double t[kFusedMaxBranches];
 };
@@ -742,6 +749,14 @@ __global__ void __launch_bounds__(KMAX * kWave) walk_small_fused(const FusedArgs
     base += (size_t)f.n_mat * K * 16;
     fl.tiptab = base;
     base += (size_t)f.n_mat * K * (S + 1) * 4;
+    // with host_rows every workgroup keeps its own status word in LDS and writes its reduction
+    // rows straight to pinned host memory; the host sums them in the order of the last step
+    __shared__ int32_t sh_status;
+    const bool to_host = f.host_rows != nullptr;
+    fl.partials = to_host ? f.host_rows : a.h.partials;
+    fl.status = to_host ? &sh_status : a.status;
+    if (threadIdx.x == 0) sh_status = 0;
+    __syncthreads();
     if constexpr ((MODE & kFusedLds) != 0) {
         fl.post = base;
         base += (size_t)f.n_post_buf * K * kWave * 4;
@@ -760,7 +775,7 @@ __global__ void __launch_bounds__(KMAX * kWave) walk_small_fused(const FusedArgs
         const int m = q / K, k = q % K;
         const double tt = f.t_dev ? f.t_dev[m] : f.t[m];
         const bool bad = !(tt >= 0.0) || isinf(tt);
-        if (bad) atomicOr(a.status, kStatusValue);
+        if (bad) atomicOr(fl.status, kStatusValue);
         pmat4<T, cptr<double>>(V, Vi, lam, a.cat_r[k] * tt, bad, S, fl.mats + (size_t)q * 16, fl.tiptab + (size_t)q * (S + 1) * 4);
     }
     __syncthreads();
@@ -768,6 +783,15 @@ __global__ void __launch_bounds__(KMAX * kWave) walk_small_fused(const FusedArgs
     // 2. the walk, for this workgroup's 64 patterns
     walk_small_body<T, KMAX, 1, MODE | kFused>(a, blockIdx.x, fl);
     static_assert(kFusedMaxBlocks <= kWave, "the last workgroup reads one column per lane");
+
+    if (to_host) {
+        // every atomicOr of the workgroup is done; the status word goes last, after a
+        // system-scope fence, so that a host that sees it also sees the rows
+        __syncthreads();
+        __threadfence_system();
+        if (threadIdx.x == 0) f.host_wg_status[blockIdx.x] = sh_status;
+        return;
+    }
 
     // 3. the last workgroup to finish sums every reduction row
     __shared__ int last;
@@ -944,6 +968,8 @@ hipError_t launch_fused_t(const Instance& I, const FusedLaunch& L) {
     f.out = L.out;
     f.out_status = L.out_status;
     f.counter = L.counter;
+    f.host_rows = L.host_rows;
+    f.host_wg_status = L.host_wg_status;
     f.n_mat = 2 * I.d.n_tips - 2;
     f.n_post_buf = I.d.n_tips - 1;
     f.n_pre_buf = L.n_pre_buf;

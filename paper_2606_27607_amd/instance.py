@@ -72,6 +72,12 @@ class Instance:
                                              ctypes.c_void_p(ws), nbytes,
                                              ctypes.c_void_p(stream), ctypes.byref(self._inst)))
         self._stream = stream
+        # torch's current stream of the device as a raw handle: the direct query costs well
+        # under a microsecond, a Stream object about two (a synchronous small call takes ~35)
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        index = self.device.index
+        self._current_stream = ((lambda: raw(index)) if raw is not None
+                                else (lambda: torch.cuda.current_stream(self.device).cuda_stream))
 
     # ------------------------------------------------------------------ plumbing
     # calls that leave the partial buffers and matrices as they were
@@ -84,7 +90,7 @@ class Instance:
         return check(self._lib, getattr(self._lib, name)(self._inst, *args), self._inst)
 
     def _bind_stream(self):
-        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        s = self._current_stream()
         if s != self._stream:
             self._call("hp_set_stream", ctypes.c_void_p(s))
             self._stream = s
