@@ -17,6 +17,7 @@ namespace {
 //   tiptab[m][k][s][x]      = P[x][s]  (s < S)     column s: the propagated one-hot tip
 //   tiptab[m][k][S][x]      = sum_y P[x][y]         the propagated all-ones (unknown) tip
 // A negative or non-finite t raises kStatusValue and writes NaN.
+// mats: P in T (null for the 16-bit precisions, whose walks read only the copies below).
 // Matrix-core path extras (null when unused): matsT[m][k][y][x] = P[x][y] in T, and 16-bit
 // copies of P and P^T in H (negative rounding residues clamped to 0 before the cast), their
 // columns in the order mcol16; for BF16 a lo part (value - hi) follows lo_off elements later.
@@ -85,7 +86,7 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
     H* m16 = static_cast<H*>(d.m16);
     H* mT16 = static_cast<H*>(d.mT16);
     const size_t base = (size_t)(m * K + k) * S_pad * S_pad;
-    T* Pm = mats + base;
+    T* Pm = mats ? mats + base : nullptr;
     T* Tt = static_cast<T*>(d.tiptab) + (size_t)(m * K + k) * (S + 1) * S_pad;
     // each thread forms a 4 x 4 block of P, so that every LDS value it reads serves four
     // products (each entry's sum still runs over j in order, as one entry per thread did)
@@ -111,7 +112,7 @@ __device__ __forceinline__ void pmat_body(const PmatDev& d, const int i, const i
             for (int c = 0; c < 4; ++c) {
                 const int x = x0 + r, y = y0 + c, e = x * S_pad + y;
                 const double pv = (x < S && y < S) ? (bad ? NAN : v[r][c]) : (bad ? NAN : 0.0);
-                Pm[e] = T(pv);
+                if (mats) Pm[e] = T(pv);
                 if (y < S) Tt[y * S_pad + x] = T(pv);
                 if (matsT) matsT[base + (size_t)y * S_pad + x] = T(pv);
                 if (m16) {
@@ -274,9 +275,11 @@ PmatDev build_pmat_desc(const Instance& I, int eigen_idx, const int32_t* d_idx) 
     d.eig = I.at<double>(L.eig) + (size_t)eigen_idx * L.eig_stride;
     d.cat_r = I.at<double>(L.cat_d);
     d.idx = d_idx;
-    d.mats = I.ws + L.mats;
+    // the 16-bit matrix-core walks read only the 16-bit copies and the tip tables: the FP32
+    // matrices are not formed for them
+    d.mats = L.mats16 ? nullptr : I.ws + L.mats;
     d.tiptab = I.ws + L.tiptab;
-    d.matsT = L.matsT ? I.ws + L.matsT : nullptr;
+    d.matsT = (L.matsT && !L.mats16) ? I.ws + L.matsT : nullptr;
     d.m16 = L.mats16 ? I.ws + L.mats16 : nullptr;
     d.mT16 = L.matsT16 ? I.ws + L.matsT16 : nullptr;
     d.qptab = L.qptab ? I.ws + L.qptab : nullptr;
