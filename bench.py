@@ -10,7 +10,8 @@ Prints one JSON line (rank 0, N = 1) with the throughput, the roofline of the do
 kernel (the traversal kernel, timed live with HIP events on the library's stream), the
 error against the FP64 oracle, synchronous-call latency percentiles, the oracle timed on a
 bounded sample of the same workload on the host cores, and the same measurements for the
-FP64 form and for the 64-taxon codon workload in FP32 / BF16 / FP16 / FP64 ("variants"),
+FP64 form, for the 64-taxon codon workload in FP32 / BF16 / FP16 / FP64 and for a 64-taxon
+amino-acid workload in FP32 / BF16x3 / BF16 / FP16 ("variants"),
 the rate-matrix gradient, the operation-level calls against one whole-tree call, the autograd
 modes, and the serving loop on 64 clients with Poisson arrivals ("serving").
 """
@@ -29,8 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "lnL+gradient evals/s vs plain FP32 at stated error; %roofline; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 # dense matrix-core peaks of MI355X per operand type, TFLOP/s
-MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f16": 2500.0, "f32": 157.3, "f64": 78.6}
-ELEM = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500.0, "f32": 157.3, "f64": 78.6}
+# bytes per stored partial element (bf16x3: FP32 partials, split-BF16 products)
+ELEM = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "bf16x3": 4}
 KERNEL_SOURCES = {True: "paper_2606_27607_amd/csrc/kernels_small.hip",
                   False: "paper_2606_27607_amd/csrc/walk_mfma.inc"}
 
@@ -759,6 +761,8 @@ def main():
         plan = [("nuc8", "f64")]
         plan += [("nuc128", "f64")] if args.workload == "nuc128" else []
         plan += [("codon64", p) for p in ("f32", "bf16", "f16", "f64")]
+        # 20 states: FP32 against the mixed forms (bf16x3 is the one held to 1e-5 on lnL)
+        plan += [("aa64", p) for p in ("f32", "bf16x3", "bf16", "f16")]
         wls = {args.workload: wl}
         for name, prec in plan:
             if (name, prec) == (args.workload, args.precision):
@@ -775,13 +779,16 @@ def main():
                     wls[name], min(CPU_SAMPLE[name], wls[name].n_patterns), all_cores=name != "nuc8",
                     repeats=21 if name == "nuc8" else 1)
         line["variants"] = variants
-        by = {(v["config"]["taxa"], v["dtype"]): v for v in variants}
-        c32 = by.get((64, "f32"))
-        if c32:
-            line["codon_mixed_vs_fp32"] = {
-                p: {"speedup_vs_f32": by[(64, p)]["value"] / c32["value"],
-                    "lnl_rel_err": by[(64, p)]["error_vs_oracle"].get("lnl_rel")}
-                for p in ("bf16", "f16") if (64, p) in by}
+        by = {(v["config"]["states"], v["dtype"]): v for v in variants}
+        for key, states, forms in (("codon_mixed_vs_fp32", 61, ("bf16", "f16")),
+                                   ("aa_mixed_vs_fp32", 20, ("bf16x3", "bf16", "f16"))):
+            ref = by.get((states, "f32"))
+            if ref:
+                line[key] = {
+                    p: {"speedup_vs_f32": by[(states, p)]["value"] / ref["value"],
+                        "lnl_rel_err": by[(states, p)]["error_vs_oracle"].get("lnl_rel"),
+                        "grad_err": by[(states, p)]["error_vs_oracle"].get("grad_maxabs_over_maxabs")}
+                    for p in forms if (states, p) in by}
         print("[bench] rate-matrix gradient", file=sys.stderr, flush=True)
         line["rate_matrix_gradient"] = (
             [measure_rate_gradient(synth.config_workload("nuc128"), p, max(10, args.steps // 2), 3)

@@ -128,8 +128,12 @@ CONFIG_SPECS = {
     "codon64": ("gy94", 64, 10_000, 0.1, 1),
     "nuc256": ("gtr", 256, 50_000, 0.05, 4),
     "codon32": ("gy94", 32, 5_000, 0.1, 1),
+    # an amino-acid stand-in beside the five configurations (20 states, random exchangeabilities
+    # and Dirichlet(1) frequencies, as the serving mix draws them), for the 20-state precision
+    # forms; seeded at SEED_BASE + 6
+    "aa64": ("aa", 64, 10_000, 0.1, 1),
 }
-CONFIG_INDEX = {"nuc8": 1, "nuc128": 2, "codon64": 3, "nuc256": 4, "codon32": 4}
+CONFIG_INDEX = {"nuc8": 1, "nuc128": 2, "codon64": 3, "nuc256": 4, "codon32": 4, "aa64": 6}
 
 
 def config_workload(name: str, n_patterns: int | None = None) -> Workload:
