@@ -518,10 +518,11 @@ def measure_autograd(wl, precision: str, steps: int, period: int = 4) -> dict:
 
 
 # Serving precisions, the fastest that keep lnL within 1e-4 relative on every client: FP32 for
-# 4 and 20 states, BF16 (FP32 exponent range) for 61.  FP16 runs faster but flushes values
-# below 2^-24 of a pattern's maximum; on large trees with very short branches that can zero a
-# site likelihood (HP_ERR_NUMERIC).  BF16 partials for 20 states measured up to 1.3e-4.
-SERVING_PRECISION = {4: "f32", 20: "f32", 61: "bf16"}
+# 4 states, FP32 partials with split-BF16 products (bf16x3) for 20, BF16 (FP32 exponent range)
+# for 61.  FP16 runs faster but flushes values below 2^-24 of a pattern's maximum; on large
+# trees with very short branches that can zero a site likelihood (HP_ERR_NUMERIC).  BF16
+# partials for 20 states measured up to 1.3e-4 on small data sets.
+SERVING_PRECISION = {4: "f32", 20: "bf16x3", 61: "bf16"}
 
 
 def _serving_client(c):
