@@ -249,11 +249,18 @@ class Instance:
         """lnL and (if want_grad) d lnL / d t_c for c = 0..2N-3; t indexed by node."""
         self._bind_stream()
         nb = 2 * self.n_tips - 2
-        tt = _f64(np.asarray(t, dtype=np.float64)[:nb], nb)
-        out = np.zeros(1)
-        g = np.zeros(nb)
-        self._call("hp_evaluate", _ptr(tt), int(bool(want_grad)), _ptr(out), _ptr(g))
-        return (float(out[0]), g) if want_grad else float(out[0])
+        if type(t) is np.ndarray and t.dtype == np.float64 and t.ndim == 1 and t.size >= nb:
+            tt = t[:nb] if t.flags.c_contiguous else np.ascontiguousarray(t[:nb])
+        else:
+            tt = _f64(np.asarray(t, dtype=np.float64)[:nb], nb)
+        # lnL and the gradients in one fresh array; pointers passed as plain integers (a
+        # synchronous small evaluation takes ~35 us, of which ctypes objects would be several)
+        out = np.empty(1 + nb)
+        base = out.__array_interface__["data"][0]
+        self.generation += 1
+        check(self._lib, self._lib.hp_evaluate(self._inst, tt.__array_interface__["data"][0], int(bool(want_grad)),
+                                               base, base + 8), self._inst)
+        return (float(out[0]), out[1:]) if want_grad else float(out[0])
 
     def evaluate_device(self, t, want_grad: bool = True, out=None):
         """Stream-ordered evaluation on device tensors: t (FP64, 2N-2) -> out (FP64, 1 + 2N-2
