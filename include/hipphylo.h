@@ -274,7 +274,7 @@ int hp_pre_gradients_device(hp_instance* inst, const hp_pre_op* ops, int count, 
  * the post- and pre-order traversals).  ops: count entries of 10 int32 each: a kind (0: a
  * post-order operation, fields hp_post_op; 1: a pre-order operation, fields hp_pre_op) and
  * its fields, unused trailing fields ignored; validated as those operations are, gradient
- * slots distinct over the list.  n_states <= 4 (HP_ERR_UNSUPPORTED otherwise).
+ * slots distinct over the list.  n_states <= 64 (HP_ERR_UNSUPPORTED on the eigensystem path).
  * Stream-ordered; the list is copied before return. */
 int hp_traverse_gradients_device(hp_instance* inst, const int32_t* ops, int count, int freq_idx,
                                  int catw_idx, int eigen_idx, double* d_grad, int n_grad);

@@ -8,14 +8,14 @@ one segment at a time, just before it needs them: the segment of a non-checkpoin
 c and every internal node below it reached without passing a checkpoint, recomputed from
 the checkpoints and tips under it.  Post-order buffers in use are then the checkpoints
 plus the segments on the current root-to-tip path, instead of N-1, at the cost of about
-one more post-order pass and one launch per segment.
+one more post-order pass.
 
-Everything runs through the operation-level calls (hp_update_post, hp_root_lnl,
-hp_pre_gradients; for four states the whole backward pass is one hp_traverse_gradients_device
-launch over the same operations as one list) of an instance created with the buffer counts
-the plan reports; the
-rescale flags are the library's own plan for the instance's scaling policy, so a
-recomputed partial is bitwise the one the forward pass produced.
+Everything runs through the operation-level calls (hp_update_post, hp_root_lnl, and for the
+backward pass one hp_traverse_gradients_device launch over the recomputations and pre-order
+operations as one list; the step-wise form, one hp_update_post or hp_pre_gradients_device
+launch per segment, gives the same bits) of an instance created with the buffer counts the
+plan reports; the rescale flags are the library's own plan for the instance's scaling
+policy, so a recomputed partial is bitwise the one the forward pass produced.
 """
 from __future__ import annotations
 
@@ -224,8 +224,9 @@ class Checkpointed:
         torch = self.inst.torch
         nb = 2 * self.plan.n_tips - 2
         acc = torch.zeros(nb, dtype=torch.float64, device=self.inst.device)
-        if self.inst.desc.n_states <= 4:
-            # the 4-state walk takes the whole backward pass as one mixed list, one launch
+        if self.inst.desc.n_states <= 64:
+            # the whole backward pass as one mixed list, one launch (the 4-state walk or the
+            # operation-level matrix-core walk)
             self.inst.traverse_gradients_device(self.plan.mixed_ops, acc)
             return acc.cpu().numpy()
         for kind, ops in self.plan.steps:

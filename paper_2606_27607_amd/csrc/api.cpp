@@ -966,8 +966,7 @@ int hp_traverse_gradients_device(hp_instance* inst, const int32_t* ops, int coun
                                  int eigen_idx, double* d_grad, int n_grad) {
     if (!inst) return HP_ERR_ARG;
     auto* I = reinterpret_cast<Instance*>(inst);
-    if (I->eig || I->S_pad != 4)
-        return fail(I, HP_ERR_UNSUPPORTED, "mixed operation lists are for n_states <= 4");
+    if (I->eig) return fail(I, HP_ERR_UNSUPPORTED, "mixed operation lists are for n_states <= 64");
     if (count < 0 || (size_t)count * hp::kMixedOpInts > (size_t)max_ops(I->d) * hp::kPreOpInts)
         return fail(I, HP_ERR_ARG, "bad operation count");
     if (count > 0 && !ops) return fail(I, HP_ERR_ARG, "ops is NULL");

@@ -228,7 +228,7 @@ class Instance:
     def traverse_gradients_device(self, ops, acc, freq_idx: int = 0, eigen_idx: int = 0, catw_idx: int = 0):
         """One launch over a list mixing post-order (kind 0) and pre-order (kind 1)
         operations, rows of 10 int32 (kind, then the operation's fields), gradients added to
-        ``acc`` as by :meth:`pre_gradients_device` (hp_traverse_gradients_device, n_states <= 4)."""
+        ``acc`` as by :meth:`pre_gradients_device` (hp_traverse_gradients_device, n_states <= 64)."""
         self._bind_stream()
         torch = self.torch
         if not (acc.is_cuda and acc.dtype == torch.float64 and acc.is_contiguous() and acc.numel() >= 1):

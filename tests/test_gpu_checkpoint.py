@@ -88,13 +88,18 @@ def test_checkpoint_autograd_mode():
     assert grad_err(t.grad.cpu().numpy() / 3.0, g_o) < 1e-9
 
 
-@pytest.mark.parametrize("precision,period", [("f64", 3), ("f32", 4), ("f32", 1000)])
-def test_one_launch_backward_equals_stepwise_calls(precision, period):
-    """For four states the backward pass runs as one mixed list (hp_traverse_gradients_device);
-    the same operations as step-wise hp_update_post / hp_pre_gradients_device calls give
-    bitwise the same gradients, and one launch is all the backward pass issues."""
-    wl = synth.make_workload("gtr", 70, 3000, seed=[20260075, period], unknown_frac=0.02)
-    ck = checkpointed(wl, period, precision, "every_k", 4)
+@pytest.mark.parametrize("kind,n,npat,precision,period", [
+    ("gtr", 70, 3000, "f64", 3), ("gtr", 70, 3000, "f32", 4), ("gtr", 70, 3000, "f32", 1000),
+    ("gy94", 26, 500, "bf16", 3), ("gy94", 26, 500, "f32", 2), ("gy94", 18, 200, "f64", 2),
+    ("aa", 30, 700, "bf16x3", 3), ("aa", 30, 700, "f16", 2)])
+def test_one_launch_backward_equals_stepwise_calls(kind, n, npat, precision, period):
+    """The backward pass runs as one mixed list (hp_traverse_gradients_device: the 4-state
+    walk, or the operation-level matrix-core walk for 20 and 61 states); the same operations
+    as step-wise hp_update_post / hp_pre_gradients_device calls give bitwise the same
+    gradients, and one launch is all the backward pass issues."""
+    wl = synth.make_workload(kind, n, npat, seed=[20260075, period, n], unknown_frac=0.02)
+    from paper_2606_27607_amd import default_scaling
+    ck = checkpointed(wl, period, precision, *default_scaling(wl.n_states, precision))
     nb = 2 * wl.n_tips - 2
     ck.lnl(wl.t)
     inst = ck.inst
