@@ -455,10 +455,11 @@ void choose_mfma_blocks(Instance* I) {
     hp::tree_shape_mfma(*I, &ct, &per_cu, &op_per_cu);
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, I->d.device) != hipSuccess)
         n_cu = 0;
-    // operation-level launches: a workgroup per tile, but no more than the pre-order kernel
-    // (the heaviest) holds at once, so that its tiles never run in a second partial round;
-    // as many as the reduction rows hold (HIPPHYLO_OP_BLOCKS overrides the count, tuning)
-    int op = I->P_pad / hp::kMfmaTile;
+    // operation-level launches: a workgroup per group of op_tiles tiles, but no more than the
+    // pre-order kernel (the heaviest) holds at once, so that its groups never run in a second
+    // partial round; as many as the reduction rows hold (HIPPHYLO_OP_BLOCKS overrides the
+    // count, tuning)
+    int op = I->P_pad / hp::kMfmaTile / hp::op_tiles(I->d.precision, I->S_pad, I->d.n_categories);
     if (op_per_cu > 0 && n_cu > 0) op = std::min(op, op_per_cu * n_cu);
     if (const char* env = std::getenv("HIPPHYLO_OP_BLOCKS")) {
         const int v = std::atoi(env);

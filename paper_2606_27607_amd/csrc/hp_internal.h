@@ -205,6 +205,14 @@ constexpr bool bf16_split(int prec) { return prec == HP_PREC_BF16 || prec == HP_
 // (the order of the partials' R2 rows); storing each block's columns as
 // [0-3, 16-19, 4-7, 20-23, 8-11, 24-27, 12-15, 28-31] makes a lane's eight values one
 // contiguous 16-byte load, at column 32 s + 8 g, which a direct load into LDS can also fetch.
+// Pattern tiles one wave of the operation-level matrix-core kernels takes together, sharing
+// every matrix fragment it loads (the kernels and the host's grid use the same count):
+// three with 64 padded states and up to 4 categories outside FP64, one otherwise (with 32
+// padded states two or three measured no faster).
+constexpr int op_tiles(int prec, int s_pad, int n_categories) {
+    return (n_categories <= 4 && prec != HP_PREC_F64 && s_pad == 64) ? 3 : 1;
+}
+
 __host__ __device__ constexpr int mcol16(int y) {
     return (y & ~31) + 8 * ((y & 15) >> 2) + 4 * ((y & 31) >> 4) + (y & 3);
 }
