@@ -124,6 +124,31 @@ __device__ __forceinline__ D load_desc(const void* p) {
     return d;
 }
 
+// The same pointer, known to the compiler to point to global memory.  Pointers read from a
+// descriptor in memory are generic, and a load through a generic pointer compiles to a flat
+// load, whose wait takes in every memory operation in flight; the batched kernels pass each
+// pointer of the descriptors they read through this (a no-op at run time).  The round trip
+// through an integer keeps the compiler from folding the two address-space casts away.
+template <typename T>
+__device__ __forceinline__ T* in_global(T* p) {
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
+__device__ __forceinline__ void globalize(DescHead& h) { h.partials = in_global(h.partials); }
+
+__device__ __forceinline__ void globalize(PmatDev& d) {
+    d.eig = in_global(d.eig);
+    d.cat_r = in_global(d.cat_r);
+    d.idx = in_global(d.idx);
+    d.mats = in_global(d.mats);
+    d.tiptab = in_global(d.tiptab);
+    d.matsT = in_global(d.matsT);
+    d.m16 = in_global(d.m16);
+    d.mT16 = in_global(d.mT16);
+    d.qptab = in_global(d.qptab);
+    d.status = in_global(d.status);
+}
+
 __device__ __forceinline__ int batch_find(const int32_t* off, int n, int block) {
     int i = 0;
     while (i + 1 < n && block >= off[i + 1]) ++i;

@@ -175,7 +175,8 @@ __global__ void __launch_bounds__(64) pmat4_kernel(const PmatDev d, const double
 template <typename T, typename H, int SMAX>
 __global__ void __launch_bounds__(256) pmat_batched(const BatchArgs b) {
     const int q = batch_find(b.pmat_off, b.n, blockIdx.x);
-    const PmatDev d = load_desc<PmatDev>(b.pmat[q]);
+    PmatDev d = load_desc<PmatDev>(b.pmat[q]);
+    globalize(d);
     const int i = blockIdx.x - b.pmat_off[q];
     pmat_body<T, H, SMAX>(d, i, blockIdx.y, b.t[q][i]);
 }
@@ -238,7 +239,8 @@ reduce_rows(const double* __restrict__ partials, int n_blocks, int first, double
 __global__ void __launch_bounds__(256) reduce_batched(const BatchArgs b) {
     __shared__ double ws[4];
     const int q = batch_find(b.red_off, b.n, blockIdx.x);
-    const DescHead h = load_desc<DescHead>(b.walk[q]);
+    DescHead h = load_desc<DescHead>(b.walk[q]);
+    globalize(h);
     const int j = blockIdx.x - b.red_off[q];
     double s = 0.0;
     for (int blk = threadIdx.x; blk < h.n_blocks; blk += blockDim.x) s += h.partials[(size_t)j * h.n_blocks + blk];

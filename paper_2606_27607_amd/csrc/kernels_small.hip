@@ -122,6 +122,28 @@ struct WalkDev {
     int q_slot;             // kQGrad: first reduction slot of the rate-matrix gradient
 };
 
+// Every pointer of a descriptor read from memory, marked as global (in_global).
+template <typename T>
+__device__ __forceinline__ void globalize(WalkDev<T>& a) {
+    globalize(a.h);
+    a.tips = in_global(a.tips);
+    a.pw = in_global(a.pw);
+    a.post = in_global(a.post);
+    a.pexp = in_global(a.pexp);
+    a.pre = in_global(a.pre);
+    a.mats = in_global(a.mats);
+    a.tiptab = in_global(a.tiptab);
+    a.Q = in_global(a.Q);
+    a.freq = in_global(a.freq);
+    a.cat_r = in_global(a.cat_r);
+    a.cat_w = in_global(a.cat_w);
+    a.post_ops = in_global(a.post_ops);
+    a.pre_ops = in_global(a.pre_ops);
+    a.site = in_global(a.site);
+    a.status = in_global(a.status);
+    a.t_mat = in_global(a.t_mat);
+}
+
 // What one child edge of an operation needs for each pattern slot of the lane: its tip
 // state, or its partial and cumulative exponent.
 template <typename T, int PPL>
@@ -707,7 +729,8 @@ template <typename T, int KMAX, int PPL, int MODE>
 __global__ void __launch_bounds__(KMAX * kWave) __attribute__((amdgpu_waves_per_eu(kSmallWavesPerEu<T, PPL, MODE>)))
 walk_small_batched(const BatchArgs b) {
     const int i = batch_find(b.walk_off, b.n, blockIdx.x);
-    const WalkDev<T> a = load_desc<WalkDev<T>>(b.walk[i]);
+    WalkDev<T> a = load_desc<WalkDev<T>>(b.walk[i]);
+    globalize(a);
     walk_small_body<T, KMAX, PPL, MODE>(a, blockIdx.x - b.walk_off[i]);
 }
 
@@ -771,12 +794,18 @@ __global__ void __launch_bounds__(KMAX * kWave) walk_small_fused(const FusedArgs
     const cptr<double> V = as_const(f.eig);
     const cptr<double> Vi = V + S * S;
     const cptr<double> lam = V + 2 * S * S;
-    for (int q = threadIdx.x; q < f.n_mat * K; q += blockDim.x) {
-        const int m = q / K, k = q % K;
-        const double tt = f.t_dev ? f.t_dev[m] : f.t[m];
+    auto form = [&](int q, double tt) {
         const bool bad = !(tt >= 0.0) || isinf(tt);
         if (bad) atomicOr(fl.status, kStatusValue);
-        pmat4<T, cptr<double>>(V, Vi, lam, a.cat_r[k] * tt, bad, S, fl.mats + (size_t)q * 16, fl.tiptab + (size_t)q * (S + 1) * 4);
+        pmat4<T, cptr<double>>(V, Vi, lam, a.cat_r[q % K] * tt, bad, S, fl.mats + (size_t)q * 16,
+                               fl.tiptab + (size_t)q * (S + 1) * 4);
+    };
+    // branch lengths from global memory or from the kernel arguments, in loops of their own:
+    // one load choosing between the two addresses would be a generic (flat) load
+    if (f.t_dev) {
+        for (int q = threadIdx.x; q < f.n_mat * K; q += blockDim.x) form(q, in_global(f.t_dev)[q / K]);
+    } else {
+        for (int q = threadIdx.x; q < f.n_mat * K; q += blockDim.x) form(q, f.t[q / K]);
     }
     __syncthreads();
 
