@@ -761,7 +761,7 @@ def main():
         # the 8-taxon FP64 case is latency-bound: its line is read for the per-call latency
         plan = [("nuc8", "f64")]
         plan += [("nuc128", "f64")] if args.workload == "nuc128" else []
-        plan += [("codon64", p) for p in ("f32", "bf16", "f16", "f64")]
+        plan += [("codon64", p) for p in ("f32", "bf16x3", "bf16", "f16", "f64")]
         # 20 states: FP32 against the mixed forms (bf16x3 is the one held to 1e-5 on lnL)
         plan += [("aa64", p) for p in ("f32", "bf16x3", "bf16", "f16")]
         wls = {args.workload: wl}
@@ -781,7 +781,7 @@ def main():
                     repeats=21 if name == "nuc8" else 1)
         line["variants"] = variants
         by = {(v["config"]["states"], v["dtype"]): v for v in variants}
-        for key, states, forms in (("codon_mixed_vs_fp32", 61, ("bf16", "f16")),
+        for key, states, forms in (("codon_mixed_vs_fp32", 61, ("bf16x3", "bf16", "f16")),
                                    ("aa_mixed_vs_fp32", 20, ("bf16x3", "bf16", "f16"))):
             ref = by.get((states, "f32"))
             if ref:
