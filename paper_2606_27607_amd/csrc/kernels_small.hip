@@ -231,6 +231,11 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
     // taken from registers (forwarding) instead of a store-load round trip.  Both keep the
     // exact values memory would have returned, so results do not change.
     constexpr bool kPf = PPL == 1;
+    // The one-launch kernel (kF) prefetches with fetch_pf, after the current operation's
+    // tip-table rows and on every operation.  Measured against the plain prefetch: the 8-taxon
+    // call 29.4 -> 28.3 us, but the 128-taxon, 100,000-pattern walk 0.671 -> 0.72 ms, whose
+    // seven waves per SIMD already hide the latency and pay for the extra loads.
+    constexpr bool kPfAll = kPf && kF;
     // partials in LDS (kFusedLds, fixed at compile time so that the accesses are LDS
     // instructions) or in the workspace
     constexpr bool lds_part = (MODE & kFusedLds) != 0;
@@ -266,6 +271,20 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 ci.v[j] = ld4(post_ptr(c, j));
                 ci.e[j] = *exp_ptr(c, j);
             }
+        }
+    };
+    // The prefetching form of fetch (kPfAll): every field is loaded on every path, from a
+    // harmless address where its value goes unused (post-order buffer 0, tip 0).  A field
+    // loaded on one path only meets its older value where the paths join, and the compiler
+    // copies the new value into place there, which waits for the load as soon as it is issued.
+    auto fetch_pf = [&](int c, int fwd, ChildIn<T, PPL>& ci) {
+        const bool tip = c < a.N, ld = !tip && c != fwd;
+        const int cv = ld ? c : a.N, cs = tip ? c : 0;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            ci.s[j] = a.tips[(size_t)cs * a.P_pad + p0 + j * kWave];
+            ci.v[j] = ld4(post_ptr(cv, j));
+            ci.e[j] = *exp_ptr(cv, j);
         }
     };
     // u = P_m x for the child (x: tip column, forwarded or loaded partial) and its exponent
@@ -444,8 +463,13 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
         int prev_e[PPL] = {};
         if (kPf && a.n_post > 0) {
             cptr<int32_t> op0 = as_const(a.post_ops);
-            fetch(op0[1], -1, in1);
-            fetch(op0[3], -1, in2);
+            if constexpr (kPfAll) {
+                fetch_pf(op0[1], -1, in1);
+                fetch_pf(op0[3], -1, in2);
+            } else {
+                fetch(op0[1], -1, in1);
+                fetch(op0[3], -1, in2);
+            }
         }
         for (int i = 0; i < a.n_post; ++i) {
             cptr<int32_t> op = as_const(a.post_ops + (size_t)i * kPostOpInts);
@@ -453,7 +477,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             if (!kPf) {
                 fetch(c1, prev, in1);
                 fetch(c2, prev, in2);
-            } else if (i + 1 < a.n_post) {
+            } else if (!kPfAll && i + 1 < a.n_post) {
                 cptr<int32_t> on = as_const(a.post_ops + (size_t)(i + 1) * kPostOpInts);
                 fetch(on[1], dest, nx1);
                 fetch(on[3], dest, nx2);
@@ -462,6 +486,16 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             int e1[PPL], e2[PPL], E[PPL];
             resolve(c1, m1, in1, prev, prev_x, prev_e, u1, e1);
             resolve(c2, m2, in2, prev, prev_x, prev_e, u2, e2);
+            // kPfAll: the next operation's inputs after this one's tip-table rows (loads
+            // complete in issue order, so the wait for those rows leaves the prefetch in
+            // flight); the last operation requests its own again, unused, so that every path
+            // issues the same loads and the compiler's wait counts stay exact
+            if constexpr (kPfAll) {
+                const int nx = i + 1 < a.n_post ? i + 1 : i;
+                cptr<int32_t> on = as_const(a.post_ops + (size_t)nx * kPostOpInts);
+                fetch_pf(on[1], dest, nx1);
+                fetch_pf(on[3], dest, nx2);
+            }
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 x[j] = mul(u1[j], u2[j]);
@@ -534,12 +568,22 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                             V4<T> (&q)[PPL]) {
             cptr<int32_t> o = as_const(a.pre_ops + (size_t)jj * kPreOpInts);
             const int pp = o[0];
-            if (pp >= 0 && pp != f1 && pp != f2) {
+            if constexpr (kPfAll) {
+                // as fetch_pf: the parent's partial, or post-order buffer 0 when unused (it
+                // always exists; a tree may have no pre-order buffer)
+                const bool ld = pp >= 0 && pp != f1 && pp != f2;
 #pragma unroll
-                for (int j = 0; j < PPL; ++j) q[j] = ld4(pre_ptr(pp, j));
+                for (int j = 0; j < PPL; ++j) q[j] = ld4(ld ? pre_ptr(pp, j) : post_ptr(a.N, j));
+                fetch_pf(o[1], -1, c1i);
+                fetch_pf(o[5], -1, c2i);
+            } else {
+                if (pp >= 0 && pp != f1 && pp != f2) {
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) q[j] = ld4(pre_ptr(pp, j));
+                }
+                fetch(o[1], -1, c1i);
+                fetch(o[5], -1, c2i);
             }
-            fetch(o[1], -1, c1i);
-            fetch(o[5], -1, c2i);
         };
         if (kPf && a.n_pre > 0) fetch_op(0, -1, -1, in1, in2, qin);
         for (int i = 0; i < a.n_pre; ++i) {
@@ -551,7 +595,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             if (!kPf) fetch_op(i, pq1, pq2, in1, in2, qin);
             if (i + 1 < a.n_pre) {
                 nxt_pp = as_const(a.pre_ops + (size_t)(i + 1) * kPreOpInts)[0];
-                if (kPf) fetch_op(i + 1, q1, q2, nx1, nx2, qnx);
+                if (kPf && !kPfAll) fetch_op(i + 1, q1, q2, nx1, nx2, qnx);
             }
             V4<T> qn[PPL], ua[PPL], ub[PPL], va[PPL], vb[PPL], qa[PPL] = {}, qb[PPL] = {};
             int e_unused[PPL], ea[PPL], eb[PPL];
@@ -561,6 +605,9 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 qn[j] = pp < 0 ? fr : (pp == pq1 ? pr1[j] : (pp == pq2 ? pr2[j] : qin[j]));
             resolve(c1, m1, in1, -1, none, none_e, ua, e_unused);
             resolve(c2, m2, in2, -1, none, none_e, ub, e_unused);
+            // kPfAll: the next operation's inputs after this one's tip-table rows (as in
+            // post-order; the last operation requests its own again)
+            if constexpr (kPfAll) fetch_op(i + 1 < a.n_pre ? i + 1 : i, q1, q2, nx1, nx2, qnx);
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 va[j] = mul(qn[j], ub[j]);
