@@ -231,10 +231,12 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
     // taken from registers (forwarding) instead of a store-load round trip.  Both keep the
     // exact values memory would have returned, so results do not change.
     constexpr bool kPf = PPL == 1;
-    // The one-launch kernel (kF) prefetches with fetch_pf, after the current operation's
-    // tip-table rows and on every operation.  Measured against the plain prefetch: the 8-taxon
-    // call 29.4 -> 28.3 us, but the 128-taxon, 100,000-pattern walk 0.671 -> 0.72 ms, whose
-    // seven waves per SIMD already hide the latency and pay for the extra loads.
+    // kLate: the next operation's inputs are requested after the current operation's
+    // tip-table rows; kPfAll: with fetch_pf, on every operation.  The one-launch kernel takes
+    // both (8-taxon call 29.4 -> 28.9 us), FP64 the first (128 taxa x 100,000 patterns 1.323 ->
+    // 1.284 ms); the FP32 walk at that size keeps the plain prefetch (0.671 ms against 0.698
+    // and 0.728): seven waves per SIMD already hide the latency there.
+    constexpr bool kLate = kPf && (kF || sizeof(T) == 8);
     constexpr bool kPfAll = kPf && kF;
     // partials in LDS (kFusedLds, fixed at compile time so that the accesses are LDS
     // instructions) or in the workspace
@@ -477,7 +479,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             if (!kPf) {
                 fetch(c1, prev, in1);
                 fetch(c2, prev, in2);
-            } else if (!kPfAll && i + 1 < a.n_post) {
+            } else if (!kLate && i + 1 < a.n_post) {
                 cptr<int32_t> on = as_const(a.post_ops + (size_t)(i + 1) * kPostOpInts);
                 fetch(on[1], dest, nx1);
                 fetch(on[3], dest, nx2);
@@ -486,15 +488,19 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             int e1[PPL], e2[PPL], E[PPL];
             resolve(c1, m1, in1, prev, prev_x, prev_e, u1, e1);
             resolve(c2, m2, in2, prev, prev_x, prev_e, u2, e2);
-            // kPfAll: the next operation's inputs after this one's tip-table rows (loads
+            // kLate: the next operation's inputs after this one's tip-table rows (loads
             // complete in issue order, so the wait for those rows leaves the prefetch in
-            // flight); the last operation requests its own again, unused, so that every path
-            // issues the same loads and the compiler's wait counts stay exact
+            // flight); with kPfAll the last operation requests its own again, unused, so that
+            // every path issues the same loads and the compiler's wait counts stay exact
             if constexpr (kPfAll) {
                 const int nx = i + 1 < a.n_post ? i + 1 : i;
                 cptr<int32_t> on = as_const(a.post_ops + (size_t)nx * kPostOpInts);
                 fetch_pf(on[1], dest, nx1);
                 fetch_pf(on[3], dest, nx2);
+            } else if (kLate && i + 1 < a.n_post) {
+                cptr<int32_t> on = as_const(a.post_ops + (size_t)(i + 1) * kPostOpInts);
+                fetch(on[1], dest, nx1);
+                fetch(on[3], dest, nx2);
             }
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
@@ -595,7 +601,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             if (!kPf) fetch_op(i, pq1, pq2, in1, in2, qin);
             if (i + 1 < a.n_pre) {
                 nxt_pp = as_const(a.pre_ops + (size_t)(i + 1) * kPreOpInts)[0];
-                if (kPf && !kPfAll) fetch_op(i + 1, q1, q2, nx1, nx2, qnx);
+                if (kPf && !kLate) fetch_op(i + 1, q1, q2, nx1, nx2, qnx);
             }
             V4<T> qn[PPL], ua[PPL], ub[PPL], va[PPL], vb[PPL], qa[PPL] = {}, qb[PPL] = {};
             int e_unused[PPL], ea[PPL], eb[PPL];
@@ -605,9 +611,10 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 qn[j] = pp < 0 ? fr : (pp == pq1 ? pr1[j] : (pp == pq2 ? pr2[j] : qin[j]));
             resolve(c1, m1, in1, -1, none, none_e, ua, e_unused);
             resolve(c2, m2, in2, -1, none, none_e, ub, e_unused);
-            // kPfAll: the next operation's inputs after this one's tip-table rows (as in
-            // post-order; the last operation requests its own again)
+            // kLate: the next operation's inputs after this one's tip-table rows (as in
+            // post-order)
             if constexpr (kPfAll) fetch_op(i + 1 < a.n_pre ? i + 1 : i, q1, q2, nx1, nx2, qnx);
+            else if (kLate && i + 1 < a.n_pre) fetch_op(i + 1, q1, q2, nx1, nx2, qnx);
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 va[j] = mul(qn[j], ub[j]);
