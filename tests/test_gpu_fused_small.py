@@ -28,7 +28,9 @@ def _three_launch(inst, t):
 
 CASES = [("nuc8", "hky", 8, 1000, 4, "f64", "every_k"), ("hky16", "hky", 16, 3000, 4, "f32", "every_k"),
          ("gtr24", "gtr", 24, 2500, 8, "f64", "every_node"), ("bin12", "bin", 12, 700, 1, "f32", "none"),
-         ("three9", "three", 9, 64, 3, "f64", "none"), ("gtr40", "gtr", 40, 4000, 4, "f32", "every_k")]
+         ("three9", "three", 9, 64, 3, "f64", "none"), ("gtr40", "gtr", 40, 4000, 4, "f32", "every_k"),
+         # the smallest trees: 2 taxa (one operation each way, no pre-order buffer) and 3
+         ("gtr2", "gtr", 2, 200, 4, "f64", "every_k"), ("gtr3", "gtr", 3, 130, 4, "f32", "every_node")]
 
 
 @pytest.mark.parametrize("name,kind,n,npat,K,precision,scaling", CASES)

@@ -146,17 +146,19 @@ def test_codon64_full_size(precision, policy):
     check(lnl, gold["lnl"], g, np.array(gold["grad"]), precision, wl.n_states, what=f"codon64 {scaling}")
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16", "f16", "bf16x3"])
 @pytest.mark.parametrize("kind,n,npat,seed", [("gy94", 360, 40, 21), ("aa", 530, 40, 22)])
 def test_large_trees_and_periodic_rescaling(precision, kind, n, npat, seed):
     """Trees whose tip states exceed the workgroup's LDS staging (N x tile-group bytes over
-    16 KiB, so tip states are read from global memory; FP64's one-tile groups still stage
-    them), each evaluated with rescaling every third level (post-order operations with no
-    exchange between the category waves, exponents forwarded from the previous operation)
-    and at every node."""
+    its staging bytes, so each operation copies its tip children's states from global memory
+    into rows of the wave's own; FP64's one-tile groups still stage them all), each evaluated
+    with rescaling every third level (post-order operations with no exchange between the
+    category waves, exponents forwarded from the previous operation) and at every node
+    (FP16 partials, with their 5-bit exponent, at every node only)."""
     wl = synth.make_workload(kind, n, npat, seed=seed, unknown_frac=0.05)
     lnl_o, _, g_o = oracle_eval(wl)
-    for scaling, period in (("every_k", 3), ("every_node", 1)):
+    policies = (("every_k", 3), ("every_node", 1)) if precision != "f16" else (("every_node", 1),)
+    for scaling, period in policies:
         inst = make_instance(wl, precision, scaling, period)
         lnl, g = inst.evaluate(wl.t)
         check(lnl, lnl_o, g, g_o, precision, wl.n_states, what=scaling)
