@@ -441,6 +441,16 @@ void choose_small_tile(Instance* I) {
     }
     I->L.tile = hp::kWave * best;
     I->L.n_blocks = I->n_blocks = (P + I->L.tile - 1) / I->L.tile;
+    // FP32 at one pattern per lane on at most half the device: the walk is short of waves to
+    // hide its latency, and loading the next operation's inputs on every path pays (50,000
+    // patterns x 256 taxa: 0.973 -> 0.902 ms); on a full device the extra loads cost more
+    // (100,000 x 128: 0.671 -> 0.700 ms).  HIPPHYLO_SMALL_PF=0|1 forces the choice.
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, I->d.device) != hipSuccess)
+        n_cu = 0;
+    const long cap = best == 1 && n_cu > 0 ? (long)hp::small_blocks_per_cu(*I, 1) * n_cu : 0;
+    I->small_pf_every = I->d.precision == HP_PREC_F32 && best == 1 && cap > 0 && 2L * I->n_blocks <= cap;
+    if (const char* env = std::getenv("HIPPHYLO_SMALL_PF")) I->small_pf_every = best == 1 && std::atoi(env) == 1;
 }
 
 // Workgroups of an operation-level traversal launch (the columns its reduction rows use).

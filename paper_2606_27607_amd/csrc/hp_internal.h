@@ -40,6 +40,8 @@ enum WalkMode : int {
                       // workgroup in LDS, last-workgroup pattern sums
     kFusedLds = 256,  // with kFused: the partial buffers in LDS too
     kMixed = 512,     // 4-state walk of one list mixing post- and pre-order operations (with kGrad)
+    kPfEvery = 1024,  // 4-state FP32 walk at one pattern per lane whose grid fills at most half
+                      // the device: the next operation's inputs loaded on every path
 };
 constexpr int kProdPerTip = 3;     // product-list entries per tip (at most 3 N - 6 products)
 constexpr int kMixedOpInts = 10;   // kind (0 post, 1 pre), then the hp_post_op / hp_pre_op fields
@@ -191,6 +193,7 @@ struct Instance {
     // workgroups of an operation-level launch on the matrix-core path: one per 16-pattern
     // tile (the whole-tree kernel's n_blocks counts groups of several tiles)
     int n_blocks_op = 0;
+    bool small_pf_every = false;  // the 4-state walk takes its kPfEvery form (choose_small_tile)
     hipStream_t stream = nullptr;
     uint8_t* ws = nullptr;
     size_t ws_bytes = 0;

@@ -17,6 +17,8 @@
 // bitwise reproducible whatever else runs on the device.
 #include <climits>
 
+#include <type_traits>
+
 #include "hp_internal.h"
 #include "lanes.h"
 #include "pmat4.h"
@@ -232,12 +234,13 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
     // exact values memory would have returned, so results do not change.
     constexpr bool kPf = PPL == 1;
     // kLate: the next operation's inputs are requested after the current operation's
-    // tip-table rows; kPfAll: with fetch_pf, on every operation.  The one-launch kernel takes
-    // both (8-taxon call 29.4 -> 28.9 us), FP64 the first (128 taxa x 100,000 patterns 1.323 ->
-    // 1.284 ms); the FP32 walk at that size keeps the plain prefetch (0.671 ms against 0.698
-    // and 0.728): seven waves per SIMD already hide the latency there.
+    // tip-table rows; kPfAll: with fetch_pf (with kLate, on every operation).  The one-launch
+    // kernel takes both (8-taxon call 29.4 -> 28.9 us), FP64 kLate (128 taxa x 100,000
+    // patterns 1.323 -> 1.284 ms), FP32 on a device it half fills kPfAll (kPfEvery); the FP32
+    // walk on a full device keeps the plain prefetch (0.671 ms against 0.698 and 0.728): seven
+    // waves per SIMD already hide the latency there.
     constexpr bool kLate = kPf && (kF || sizeof(T) == 8);
-    constexpr bool kPfAll = kPf && kF;
+    constexpr bool kPfAll = kPf && (kF || (MODE & kPfEvery) != 0);
     // partials in LDS (kFusedLds, fixed at compile time so that the accesses are LDS
     // instructions) or in the workspace
     constexpr bool lds_part = (MODE & kFusedLds) != 0;
@@ -481,8 +484,13 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
                 fetch(c2, prev, in2);
             } else if (!kLate && i + 1 < a.n_post) {
                 cptr<int32_t> on = as_const(a.post_ops + (size_t)(i + 1) * kPostOpInts);
-                fetch(on[1], dest, nx1);
-                fetch(on[3], dest, nx2);
+                if constexpr (kPfAll) {
+                    fetch_pf(on[1], dest, nx1);
+                    fetch_pf(on[3], dest, nx2);
+                } else {
+                    fetch(on[1], dest, nx1);
+                    fetch(on[3], dest, nx2);
+                }
             }
             V4<T> u1[PPL], u2[PPL], x[PPL];
             int e1[PPL], e2[PPL], E[PPL];
@@ -492,7 +500,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             // complete in issue order, so the wait for those rows leaves the prefetch in
             // flight); with kPfAll the last operation requests its own again, unused, so that
             // every path issues the same loads and the compiler's wait counts stay exact
-            if constexpr (kPfAll) {
+            if constexpr (kPfAll && kLate) {
                 const int nx = i + 1 < a.n_post ? i + 1 : i;
                 cptr<int32_t> on = as_const(a.post_ops + (size_t)nx * kPostOpInts);
                 fetch_pf(on[1], dest, nx1);
@@ -613,7 +621,7 @@ __device__ __forceinline__ void walk_small_body(const WalkDev<T>& a, const int b
             resolve(c2, m2, in2, -1, none, none_e, ub, e_unused);
             // kLate: the next operation's inputs after this one's tip-table rows (as in
             // post-order)
-            if constexpr (kPfAll) fetch_op(i + 1 < a.n_pre ? i + 1 : i, q1, q2, nx1, nx2, qnx);
+            if constexpr (kPfAll && kLate) fetch_op(i + 1 < a.n_pre ? i + 1 : i, q1, q2, nx1, nx2, qnx);
             else if (kLate && i + 1 < a.n_pre) fetch_op(i + 1, q1, q2, nx1, nx2, qnx);
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
@@ -957,6 +965,18 @@ hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
     const WalkDev<T> a = make_desc<T>(I, w);
     dim3 grid(I.n_blocks), block(kWave * I.d.n_categories);
 #define HP_LAUNCH(M) hipLaunchKernelGGL((walk_small<T, KMAX, PPL, M>), grid, block, 0, I.stream, a)
+    if constexpr (std::is_same_v<T, float> && PPL == 1) {
+        if (I.small_pf_every) {
+            switch (w.mode) {
+                case kPost | kRootFused: HP_LAUNCH(kPost | kRootFused | kPfEvery); return hipGetLastError();
+                case kPre | kGrad: HP_LAUNCH(kPre | kGrad | kPfEvery); return hipGetLastError();
+                case kPost | kRootFused | kPre | kGrad:
+                    HP_LAUNCH(kPost | kRootFused | kPre | kGrad | kPfEvery);
+                    return hipGetLastError();
+                default: break;
+            }
+        }
+    }
     switch (w.mode) {
         case kPost: HP_LAUNCH(kPost); break;
         case kPost | kRootFused: HP_LAUNCH(kPost | kRootFused); break;
