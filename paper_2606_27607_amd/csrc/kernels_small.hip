@@ -968,6 +968,7 @@ hipError_t dispatch_walk(const Instance& I, const WalkArgs& w) {
     if constexpr (std::is_same_v<T, float> && PPL == 1) {
         if (I.small_pf_every) {
             switch (w.mode) {
+                case kPost: HP_LAUNCH(kPost | kPfEvery); return hipGetLastError();
                 case kPost | kRootFused: HP_LAUNCH(kPost | kRootFused | kPfEvery); return hipGetLastError();
                 case kPre | kGrad: HP_LAUNCH(kPre | kGrad | kPfEvery); return hipGetLastError();
                 case kPost | kRootFused | kPre | kGrad:
