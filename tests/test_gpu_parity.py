@@ -217,6 +217,37 @@ def test_tile_shapes_match_oracle(force_small_ppl, ppl, precision, kind, n, npat
     assert np.allclose(site[:npat], site_o, rtol=tol[0] * 10, atol=0)
 
 
+@pytest.mark.parametrize("K", [4, 8])
+def test_small_walk_prefetch_forms_bitwise_equal(monkeypatch, K):
+    """The FP32 4-state walk's two prefetch forms (the next operation's inputs loaded on every
+    path, which instances on a half-filled device take, and the plain one) give bitwise the
+    same lnL and gradients, in the fused, store and operation-level modes, and match the
+    oracle."""
+    import torch
+    wl = synth.make_workload("gtr", 40, 3000, seed=[20260075, K], n_categories=K, unknown_frac=0.03)
+    nb = 2 * wl.n_tips - 2
+    out = []
+    monkeypatch.setenv("HIPPHYLO_SMALL_PPL", "1")
+    for pf in ("0", "1"):
+        monkeypatch.setenv("HIPPHYLO_SMALL_PF", pf)
+        announce(f"4-state prefetch form {pf}, K={K}")
+        inst = make_instance(wl, "f32", "every_k", 4)
+        lnl, g = inst.evaluate(wl.t)
+        td = torch.tensor(wl.t[:nb], dtype=torch.float64, device=inst.device)
+        fwd = inst.evaluate_device(td, want_grad=False).cpu().numpy()
+        st = inst.gradients_device().cpu().numpy()
+        inst.update_matrices(np.arange(nb), wl.t[:nb])
+        inst.update_post(post_ops(wl.tree.children, wl.n_tips, rescale=1))
+        lop = inst.root_lnl(nb)
+        out.append((lnl, g, fwd, st, lop))
+        inst.close()
+    a, b = out
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4]
+    lnl_o, _, g_o = oracle_eval(wl)
+    check(b[0], lnl_o, b[1], g_o, "f32", wl.n_states, what="every-path prefetch")
+
+
 def test_tile_choice_and_batch_tile_check(force_small_ppl):
     """The automatic tile fills whole rounds: 131,072 patterns (2,048 one-pattern
     workgroups, more than the device holds at once in FP32) take the two-pattern tile, and
